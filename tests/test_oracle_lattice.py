@@ -1,0 +1,212 @@
+"""Pins of the oracle's lattice update (streaming, walls, lid, residual sums).
+
+Checked against closed forms and invariants: conservation on a periodic
+lattice, shear-wave and Taylor-Green decay with the paper's viscosity
+relation, the advection speed of a transverse wave, exact Couette flow,
+the first step of the moving-lid cavity worked by hand, mirror symmetry,
+a cavity at rest, and the paper's stability contrast between SRT and SmrtLBM.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+
+
+def grid(nx, ny):
+    y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    return x, y
+
+
+def moments_total(f):
+    ex, ey, _, _ = O.constants()
+    return f.sum(), (f * ex).sum(), (f * ey).sum()
+
+
+@pytest.mark.parametrize("scheme", ["srt", "smrt", "trt"])
+def test_periodic_conserves_mass_and_momentum(scheme):
+    rng = np.random.default_rng(7)
+    L = O.Lattice(32, 24, scheme, tau=0.53, tau_s=0.8, boundary="periodic")
+    _, _, w, _ = O.constants()
+    f0 = w * (1.0 + 0.02 * rng.uniform(-1, 1, size=L.shape))
+    m0 = moments_total(f0)
+    f = L.run(f0, 300)
+    m1 = moments_total(f)
+    assert abs(m1[0] - m0[0]) < 1e-12 * m0[0]
+    assert abs(m1[1] - m0[1]) < 1e-12 * m0[0] and abs(m1[2] - m0[2]) < 1e-12 * m0[0]
+
+
+def test_streaming_moves_each_population_along_its_velocity():
+    ex, ey, _, _ = O.constants()
+    L = O.Lattice(7, 5, "srt", tau=1.0, boundary="periodic")
+    for a in range(9):
+        f = np.zeros(L.shape)
+        f[2, 3, a] = 1.0
+        g = L.stream(f)
+        assert g[(2 + ey[a]) % 5, (3 + ex[a]) % 7, a] == 1.0 and g.sum() == 1.0
+    # wrap-around at the corner
+    f = np.zeros(L.shape)
+    f[4, 6, 5] = 1.0
+    assert L.stream(f)[0, 0, 5] == 1.0
+
+
+def test_streaming_bounces_back_at_walls():
+    _, _, w, opp = O.constants()
+    L = O.Lattice(4, 3, "srt", tau=1.0, u_lid=0.0, boundary="cavity")
+    f = np.zeros(L.shape)
+    f[0, 0, 7] = 1.0          # moving to (-1,-1): hits the bottom-left corner
+    f[1, 3, 1] = 1.0          # moving to (4,1): hits the right wall
+    g = L.stream(f)
+    assert g[0, 0, opp[7]] == 1.0 and g[1, 3, opp[1]] == 1.0 and g.sum() == 2.0
+
+
+@pytest.mark.parametrize("scheme", ["srt", "smrt"])
+@pytest.mark.parametrize("tau", [0.6, 1.0, 1.5])
+def test_shear_wave_decay_matches_viscosity_relation(scheme, tau):
+    """u_x = u0 sin(k y) decays as exp(-nu k^2 t), nu = (2 tau - 1)/6."""
+    errs = []
+    for n in (32, 64):
+        L = O.Lattice(n, n, scheme, tau=tau, boundary="periodic")
+        _, y = grid(n, n)
+        k = 2 * np.pi / n
+        f = L.init_equilibrium(None, 0.05 * np.sin(k * y), None)
+        nu = (2 * tau - 1) / 6
+        T = int(round(1 / (nu * k * k)))
+        f = L.run(f, T // 4)
+        a0 = (L.fields(f)[1] * np.sin(k * y)).sum()
+        f = L.run(f, T)
+        a1 = (L.fields(f)[1] * np.sin(k * y)).sum()
+        errs.append(abs(np.log(a0 / a1) / (k * k * T) / nu - 1))
+    assert errs[0] < 1.2e-2 and errs[1] < 3e-3
+    # second-order convergence in k: halving k cuts the error about four times
+    assert errs[1] < errs[0] / 3.0 or errs[0] < 1e-5
+
+
+@pytest.mark.parametrize("scheme", ["srt", "smrt"])
+def test_taylor_green_decay(scheme):
+    n, tau, u0 = 48, 0.8, 0.03
+    L = O.Lattice(n, n, scheme, tau=tau, boundary="periodic")
+    x, y = grid(n, n)
+    k = 2 * np.pi / n
+    ux = -u0 * np.cos(k * x) * np.sin(k * y)
+    uy = u0 * np.sin(k * x) * np.cos(k * y)
+    rho = 1.0 - 0.75 * u0 * u0 * (np.cos(2 * k * x) + np.cos(2 * k * y))
+    f = L.run(L.init_equilibrium(rho, ux, uy), 400)
+    _, gx, gy = L.fields(f)
+    nu = (2 * tau - 1) / 6
+    decay = np.exp(-2 * nu * k * k * 400)
+    amp = (gx * ux + gy * uy).sum() / (ux * ux + uy * uy).sum()
+    # measured viscosity within 0.3 % of (2 tau - 1)/6 at 48 nodes per wavelength
+    assert abs(np.log(amp) / np.log(decay) - 1) < 3e-3
+
+
+@pytest.mark.parametrize("scheme", ["srt", "smrt"])
+def test_transverse_wave_is_advected_by_the_mean_flow(scheme):
+    """u_y = u0 sin(k (x - V t)): pins the direction in which populations stream."""
+    n, V, u0, t = 64, 0.05, 0.01, 400
+    L = O.Lattice(n, 4, scheme, tau=0.6, boundary="periodic")
+    x, _ = grid(n, 4)
+    k = 2 * np.pi / n
+    f = L.run(L.init_equilibrium(None, V * np.ones_like(x), u0 * np.sin(k * x)), t)
+    uy = L.fields(f)[2][0]
+    c, s = (uy * np.cos(k * x[0])).sum(), (uy * np.sin(k * x[0])).sum()
+    phase = np.arctan2(-c, s)
+    assert abs(phase / (k * V * t) - 1) < 2e-3
+
+
+@pytest.mark.parametrize("tau", [0.6, 1.0, 1.7])
+def test_couette_flow_is_linear_with_srt(tau):
+    """Walls half a link outside the first and last rows: u_x = U (y + 1/2)/ny."""
+    ny, U = 8, 0.1
+    L = O.Lattice(4, ny, "srt", tau=tau, u_lid=U, boundary="channel")
+    f = L.run(L.init_equilibrium(), 20000)
+    rho, ux, uy = L.fields(f)
+    want = U * (np.arange(ny) + 0.5) / ny
+    assert np.max(np.abs(ux - want[:, None])) < 1e-11
+    assert np.max(np.abs(uy)) < 1e-12
+
+
+@pytest.mark.parametrize("scheme", ["smrt", "trt"])
+def test_couette_flow_smrt_deviates_only_at_second_order_in_u(scheme):
+    ny, errs = 8, []
+    for U in (1e-2, 1e-3):
+        L = O.Lattice(4, ny, scheme, tau=0.6, tau_s=0.8, u_lid=U, boundary="channel")
+        ux = L.fields(L.run(L.init_equilibrium(), 20000))[1]
+        errs.append(np.max(np.abs(ux[:, 0] - U * (np.arange(ny) + 0.5) / ny)) / U)
+    assert errs[0] < 1e-4 and abs(errs[0] / errs[1] - 100) < 5
+
+
+def test_cavity_at_rest_stays_exactly_at_rest():
+    L = O.Lattice(12, 10, "smrt", tau=0.55, u_lid=0.0)
+    f0 = L.init_equilibrium()
+    f = L.run(f0, 50)
+    _, ux, uy = L.fields(f)
+    # velocities stay exactly zero; populations move only by round-off of rho
+    assert not ux.any() and not uy.any()
+    assert np.max(np.abs(f - f0)) < 1e-15
+
+
+def test_cavity_first_step_by_hand():
+    """From rest, one step: only the lid links change, f_7 -= U/6, f_8 += U/6 on the
+    top row (corners too); everything else keeps its weight."""
+    U = 0.1
+    _, _, w, _ = O.constants()
+    for scheme in ("srt", "smrt"):
+        L = O.Lattice(6, 5, scheme, tau=0.7, u_lid=U)
+        f = L.run(L.init_equilibrium(), 1)
+        want = np.broadcast_to(w, L.shape).copy()
+        want[-1, :, 7] -= U / 6
+        want[-1, :, 8] += U / 6
+        assert np.max(np.abs(f - want)) < 4e-16
+
+
+@pytest.mark.parametrize("scheme", ["srt", "smrt"])
+def test_cavity_conserves_mass(scheme):
+    L = O.Lattice(32, 32, scheme, re=100, u_lid=0.1)
+    f = L.run(L.init_equilibrium(), 2000)
+    rho = L.fields(f)[0]
+    assert abs(rho.sum() / (32 * 32) - 1) < 1e-12
+
+
+@pytest.mark.parametrize("scheme", ["srt", "smrt"])
+def test_cavity_mirror_symmetry(scheme):
+    """Reversing the lid mirrors the flow: x -> nx-1-x, u_x -> -u_x."""
+    a = O.Lattice(24, 20, scheme, tau=0.62, u_lid=0.1)
+    b = O.Lattice(24, 20, scheme, tau=0.62, u_lid=-0.1)
+    _, ax, ay = a.fields(a.run(a.init_equilibrium(), 800))
+    _, bx, by = b.fields(b.run(b.init_equilibrium(), 800))
+    assert np.max(np.abs(bx[:, ::-1] + ax)) < 1e-15
+    assert np.max(np.abs(by[:, ::-1] - ay)) < 1e-15
+
+
+def test_cavity_lid_drives_a_clockwise_vortex():
+    L = O.Lattice(32, 32, "smrt", re=100, u_lid=0.1)
+    _, ux, uy = L.fields(L.run(L.init_equilibrium(), 3000))
+    assert ux[-1].mean() > 0.05          # the top row follows the lid
+    assert ux[4].mean() < 0              # return flow near the bottom
+    assert uy[:, 4].mean() > 0 > uy[:, -5].mean()
+
+
+@pytest.mark.slow
+def test_stability_contrast_srt_vs_smrt():
+    """At tau = 0.51 and a fast lid, SRT blows up within 1000 steps while SmrtLBM
+    stays finite: the qualitative stability claim of the cavity section."""
+    srt = O.Lattice(100, 100, "srt", tau=0.51, u_lid=0.1667)
+    f = srt.run(srt.init_equilibrium(), 1000)
+    assert not np.isfinite(srt.fields(f)[1]).all()
+    smrt = O.Lattice(100, 100, "smrt", tau=0.51, u_lid=0.1667)
+    f = smrt.run(smrt.init_equilibrium(), 5000)
+    _, ux, uy = smrt.fields(f)
+    assert np.isfinite(ux).all() and np.abs(ux).max() < 0.5
+
+
+def test_reduce_sums_and_nonfinite_count():
+    rho = np.array([1.0, 2.0, 3.0, 4.0])
+    ux = np.array([0.0, 1.0, 0.0, 2.0])
+    uy = np.array([1.0, 0.0, 0.0, np.nan])
+    sx = np.zeros(4)
+    sy = np.array([1.0, 1.0, 0.0, 0.0])
+    du2, u2, mass, bad = O.reduce(rho, ux, uy, sx, sy)
+    assert mass == 10.0 and bad == 1.0 and np.isnan(du2)
+    du2, u2, mass, bad = O.reduce(rho[:3], ux[:3], uy[:3], sx[:3], sy[:3])
+    assert (du2, u2, mass, bad) == (2.0, 2.0, 6.0, 0.0)
+    assert abs(O.residual(ux[:3], uy[:3], sx[:3], sy[:3], 4) - np.sqrt(2) / (4 * np.sqrt(2))) < 1e-16
