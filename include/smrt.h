@@ -1,0 +1,180 @@
+/*
+ * smrt.h -- C ABI of the MI355X (gfx950) D2Q9 lattice Boltzmann library for
+ * the single MRT-featured collision (SmrtLBM) and the single-relaxation-time
+ * (SRT/BGK) collision of Zhou, "Single MRT-featured Lattice Boltzmann Method"
+ * (arXiv:2409.01076).
+ *
+ * What one step computes (lattice units, dx = dt = e = 1):
+ *   streaming   f_a(x, t+1) = f*_a(x - e_a, t), the left-hand side of
+ *               Eq. (lb.srt) / Eq. (SmrtLBM-1) written in pull form;
+ *   moments     rho = sum_a f_a, u = sum_a e_a f_a / rho           (Eq. fea-0);
+ *   equilibrium f^eq_a(rho, u)                                     (Eq. feq-full);
+ *   collision   SRT     f* = f - (f - f^eq)/tau                    (Eq. lb.srt)
+ *               SmrtLBM f*_a = f^eq_a + (-1)^a (1 - 1/tau) C_g(a)  (Eq. SmrtLBM-1,
+ *                       with the group sums C_1, C_2 of Eq. sigma1-2-0)
+ *               TRT     f*_a = f_a - (f_a - f^eq_a)/tau_s
+ *                              + (-1)^a (1/tau_s - 1/tau) C_g(a)   (Eq. SmrtLBM-lb.1.5)
+ *   walls       cavity: the "standard bounce-back" of the cavity section, read as
+ *               half-way bounce-back (walls half a link outside the outer nodes);
+ *               the top wall moves at (u_lid, 0) and adds 6 w_a (e_a . u_w) to the
+ *               bounced population (moving-wall bounce-back, wall density 1); links
+ *               that end in the row above the top nodes, corners included, end on
+ *               the lid.  periodic: both axes wrap.
+ *
+ * Layout: the library stores the post-collision populations as deviations
+ * d_a = f*_a - w_a in structure-of-arrays planes (one plane per direction,
+ * rows of nx nodes, x fastest, y = 0 the bottom row) inside a device workspace.
+ * Every array passed in or out below is a dense device array: fields are
+ * [ny][nx], populations are [9][ny][nx] full values f (not deviations).
+ *
+ * Threads and streams: a context is used by one host thread at a time.  All
+ * device work is enqueued on the stream given at creation (NULL = the default
+ * stream); calls return without waiting unless stated.
+ *
+ * Errors: every int-returning call returns SMRT_OK (0) or a negative
+ * smrt_status; smrt_last_error() then gives a message for the calling thread.
+ * No C++ exception crosses this interface.
+ */
+#ifndef SMRT_H
+#define SMRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum smrt_status {
+    SMRT_OK = 0,
+    SMRT_EINVAL = -1,    /* invalid argument (size, enum, relaxation time, pointer) */
+    SMRT_ENOMEM = -2,    /* workspace too small or allocation failed               */
+    SMRT_EDEVICE = -3,   /* a HIP runtime call or kernel launch failed             */
+    SMRT_EUNSTABLE = -4, /* the state holds a non-finite density or velocity       */
+    SMRT_ESTATE = -5     /* call not valid in the current state                    */
+} smrt_status;
+
+typedef enum smrt_scheme {
+    SMRT_SCHEME_SRT = 0,  /* Eq. (lb.srt)          */
+    SMRT_SCHEME_SMRT = 1, /* Eq. (SmrtLBM-1)       */
+    SMRT_SCHEME_TRT = 2   /* Eq. (SmrtLBM-lb.1.5)  */
+} smrt_scheme;
+
+typedef enum smrt_boundary {
+    SMRT_CAVITY = 0,  /* lid-driven square cavity of the paper's test section */
+    SMRT_PERIODIC = 1 /* both axes wrap around                                */
+} smrt_boundary;
+
+typedef enum smrt_dtype {
+    SMRT_F64 = 0,
+    SMRT_F32 = 1,
+    SMRT_F16 = 2, /* storage only: IEEE binary16 deviations, FP32 arithmetic */
+    SMRT_BF16 = 3 /* storage only: bfloat16 deviations, FP32 arithmetic      */
+} smrt_dtype;
+
+typedef struct smrt_params {
+    int32_t nx, ny;    /* lattice nodes along x and y, each >= 3             */
+    int32_t scheme;    /* smrt_scheme                                        */
+    int32_t boundary;  /* smrt_boundary                                      */
+    int32_t storage;   /* smrt_dtype of the stored populations; arithmetic is
+                          FP64 for SMRT_F64 and FP32 otherwise                */
+    int32_t reserved0; /* must be 0                                          */
+    double tau;        /* > 1/2: used as given.  <= 0: derived from re as
+                          tau = 3 |u_lid| nx / re + 1/2, i.e.
+                          Eq. (relation-chapman-viscosity) with
+                          nu = |u_lid| nx / re                               */
+    double re;         /* Reynolds number, used only when tau <= 0           */
+    double u_lid;      /* lid speed (cavity), |u_lid| < 1/sqrt(3)            */
+    double tau_s;      /* TRT only: relaxation time of the other moments, > 1/2 */
+    void* stream;      /* hipStream_t, NULL for the default stream           */
+    int64_t reserved[4]; /* must be 0                                        */
+} smrt_params;
+
+typedef struct smrt_ctx smrt_ctx;
+
+/* Device workspace bytes needed by a context with these parameters (two
+ * population buffers, the residual snapshot and reduction scratch); 0 if the
+ * parameters are invalid.  Pure host computation. */
+size_t smrt_workspace_bytes(const smrt_params* p);
+
+/* Creates a context and sets the cold start f = f^eq(rho = 1, u = 0), t = 0.
+ * dev_ws: caller-owned device memory of at least smrt_workspace_bytes(p)
+ * bytes, 256-byte aligned, kept alive until smrt_destroy; or NULL to let the
+ * library allocate (and later free) it.  ws_bytes is ignored when dev_ws is
+ * NULL.  SMRT_EINVAL: nx or ny < 3, unknown enum, relaxation time <= 1/2,
+ * |u_lid| >= 1/sqrt(3), non-zero reserved fields, out == NULL.  SMRT_ENOMEM:
+ * ws_bytes too small or the allocation failed.  On error *out is NULL. */
+int smrt_create(const smrt_params* p, void* dev_ws, size_t ws_bytes, smrt_ctx** out);
+
+/* Sets f = f^eq(rho, u) at every node from dense device fields [ny][nx] of
+ * dtype SMRT_F32 or SMRT_F64 (Eq. feq-full); rho == NULL means 1 everywhere,
+ * ux/uy == NULL mean 0.  Resets the step counter and the residual snapshot. */
+int smrt_init_fields(smrt_ctx* c, const void* rho, const void* ux, const void* uy,
+                     int32_t dtype);
+
+/* Replaces the state by the post-collision populations f (device,
+ * [9][ny][nx], SMRT_F32 or SMRT_F64, full values), e.g. to resume a run;
+ * resets the step counter and the residual snapshot.  Values are rounded to
+ * the storage type. */
+int smrt_set_populations(smrt_ctx* c, const void* f, int32_t dtype);
+
+/* Writes the current post-collision populations f = w + d (device,
+ * [9][ny][nx], SMRT_F32 or SMRT_F64). */
+int smrt_get_populations(smrt_ctx* c, void* f, int32_t dtype);
+
+/* Enqueues n time steps (streaming, walls, moments, equilibrium, collision,
+ * store).  n == 0 does nothing; n < 0 is SMRT_EINVAL.  Asynchronous. */
+int smrt_step(smrt_ctx* c, int64_t n);
+
+/* Writes rho, ux, uy of the current state (Eq. fea-0) into dense device
+ * arrays [ny][nx] of dtype SMRT_F32 or SMRT_F64; any pointer may be NULL to
+ * skip that field.  The moments of the stored post-collision populations equal
+ * those of the pre-collision ones because the collision conserves density and
+ * momentum.  Asynchronous. */
+int smrt_moments(smrt_ctx* c, void* rho, void* ux, void* uy, int32_t dtype);
+
+/* Steady-state residual over the window since the last snapshot:
+ *   R = ||u(t) - u(t_snap)||_2 / ((t - t_snap) ||u(t)||_2),
+ * summed in FP64 in a fixed order; then u(t) becomes the new snapshot.
+ * Synchronizes the stream.  SMRT_ESTATE if no step ran since the snapshot;
+ * SMRT_EUNSTABLE (and *out = NaN) if any density or velocity is not finite.
+ * R is 0 for a lattice at rest that did not move. */
+int smrt_residual(smrt_ctx* c, double* out);
+
+/* Total mass sum rho in FP64, fixed summation order.  Synchronizes the
+ * stream.  SMRT_EUNSTABLE (and *out = NaN) on a non-finite value. */
+int smrt_mass(smrt_ctx* c, double* out);
+
+/* Steps taken since creation or the last state reset. */
+int64_t smrt_steps_done(const smrt_ctx* c);
+
+/* Relaxation time in use (after the Re mapping); NaN for c == NULL. */
+double smrt_tau(const smrt_ctx* c);
+
+/* Threads per block along x and y, and rows per thread, for the
+ * stream-collide kernel (tuning; results do not depend on it).  bx * by must
+ * be 64, 128, 256, 512 or 1024 and bx a multiple of 16; rows in 1..8.
+ * SMRT_EINVAL otherwise. */
+int smrt_set_launch(smrt_ctx* c, int32_t bx, int32_t by, int32_t rows);
+
+/* Waits for all work enqueued on the context's stream. */
+int smrt_synchronize(smrt_ctx* c);
+
+/* Frees what the library allocated; never frees a caller's workspace or
+ * stream.  NULL is a no-op.  Does not wait for enqueued work: synchronize
+ * first if the workspace is about to be reused. */
+void smrt_destroy(smrt_ctx* c);
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char* smrt_last_error(void);
+
+/* Bandwidth reference: copies `bytes` (a multiple of 16) from src to dst,
+ * both device pointers 16-byte aligned, with a plain streaming copy kernel on
+ * `stream`.  Used to calibrate byte counters and as the attainable read+write
+ * ceiling beside the stream-collide kernel.  Asynchronous. */
+int smrt_copy_kernel(const void* src, void* dst, size_t bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

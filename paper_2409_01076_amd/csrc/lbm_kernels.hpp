@@ -1,0 +1,461 @@
+// lbm_kernels.hpp -- gfx950 device code for the D2Q9 SRT / SmrtLBM update.
+//
+// State: post-collision populations stored as deviations d_a = f*_a - w_a in
+// nine structure-of-arrays planes.  Element (x, y) of plane a sits at
+// a * plane + y * pitch + x.  Two such buffers alternate (ping-pong), so every
+// step reads one buffer and writes the other: inputs are read-only and each
+// output element has exactly one writer.
+//
+// The stream-collide kernel is a pull scheme: node x gathers d_a(x - e_a) from
+// the previous step, which is the streaming half of Eq. (lb.srt) /
+// Eq. (SmrtLBM-1), then forms the moments (Eq. fea-0), the equilibrium
+// (Eq. feq-full) and the collision, and writes nine aligned values.  It is
+// bound by HBM traffic: 9 loads and 9 stores per node, about 100 flops.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace smrt {
+
+enum { SRT = 0, SMRT = 1, TRT = 2 };
+enum { CAVITY = 0, PERIODIC = 1 };
+
+// bfloat16 storage: the upper half of an IEEE binary32.
+struct bf16 {
+    uint16_t bits;
+};
+
+// Storage traits: how a stored population converts to and from the
+// arithmetic type.  FP64 storage computes in FP64, everything else in FP32.
+template <typename T> struct Storage;
+
+template <> struct Storage<double> {
+    using C = double;
+    static __device__ __forceinline__ C load(const double* p) { return *p; }
+    static __device__ __forceinline__ void store(double* p, C v) { __builtin_nontemporal_store(v, p); }
+    static __device__ __forceinline__ double to_f64(const double* p) { return *p; }
+    static __device__ __forceinline__ void from_f64(double* p, double v) { *p = v; }
+};
+
+template <> struct Storage<float> {
+    using C = float;
+    static __device__ __forceinline__ C load(const float* p) { return *p; }
+    static __device__ __forceinline__ void store(float* p, C v) { __builtin_nontemporal_store(v, p); }
+    static __device__ __forceinline__ double to_f64(const float* p) { return (double)*p; }
+    static __device__ __forceinline__ void from_f64(float* p, double v) { *p = (float)v; }
+};
+
+template <> struct Storage<_Float16> {
+    using C = float;
+    static __device__ __forceinline__ C load(const _Float16* p) { return (float)*p; }
+    static __device__ __forceinline__ void store(_Float16* p, C v)
+    {
+        __builtin_nontemporal_store((_Float16)v, p);
+    }
+    static __device__ __forceinline__ double to_f64(const _Float16* p) { return (double)(float)*p; }
+    static __device__ __forceinline__ void from_f64(_Float16* p, double v) { *p = (_Float16)(float)v; }
+};
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// Round-to-nearest-even binary32 -> bfloat16 (NaN kept quiet).
+__device__ __forceinline__ uint16_t f32_to_bf16(float v)
+{
+    uint32_t u = __float_as_uint(v);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+template <> struct Storage<bf16> {
+    using C = float;
+    static __device__ __forceinline__ C load(const bf16* p) { return bf16_to_f32(p->bits); }
+    static __device__ __forceinline__ void store(bf16* p, C v)
+    {
+        __builtin_nontemporal_store(f32_to_bf16(v), &p->bits);
+    }
+    static __device__ __forceinline__ double to_f64(const bf16* p) { return (double)bf16_to_f32(p->bits); }
+    static __device__ __forceinline__ void from_f64(bf16* p, double v) { p->bits = f32_to_bf16((float)v); }
+};
+
+// D2Q9 in the paper's order; OPP[a] is the direction with e = -e_a.
+__device__ constexpr int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__device__ constexpr int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+__device__ constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+template <typename C> struct W {
+    static constexpr C rest = C(4) / C(9);
+    static constexpr C axis = C(1) / C(9);
+    static constexpr C diag = C(1) / C(36);
+};
+
+__device__ __forceinline__ double weight_f64(int a)
+{
+    return a == 0 ? 4.0 / 9.0 : (a <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
+}
+
+struct Geom {
+    int nx, ny;
+    int pitch;     // elements per row (>= nx)
+    int64_t plane; // elements per direction plane
+    int bx, by, rows;
+    int tiles_x;   // tiles along x
+};
+
+template <typename C> struct Coef {
+    C omega;   // 1/tau
+    C omega_s; // 1/tau_s (TRT)
+    C a;       // 1 - 1/tau (SmrtLBM)
+    C b;       // 1/tau_s - 1/tau (TRT)
+    C lid;     // 6 w_diag u_lid = u_lid / 6: the moving-lid term of a diagonal link
+};
+
+// Workgroups are dealt to the 8 XCDs round-robin.  Renumber them so that each
+// XCD receives one contiguous range of tiles: vertically adjacent tiles then
+// share an L2 and the rows above and below a tile are fetched from HBM once.
+__device__ __forceinline__ int xcd_contiguous(int bid, int nblocks)
+{
+    constexpr int NXCD = 8;
+    const int xcd = bid % NXCD, local = bid / NXCD;
+    const int per = nblocks / NXCD, rem = nblocks % NXCD;
+    return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
+}
+
+// Moments, equilibrium deviation and collision of one node, in deviation form.
+// With j = rho u and drho = rho - 1 (sum_a w_a e_a = 0, sum_a w_a = 1):
+//   drho = sum_a d_a,  j = sum_a e_a d_a,
+//   f^eq_a - w_a = w_a (drho + 3 e_a.j + 9/2 (e_a.j)(e_a.u) - 3/2 j.u),
+// an exact rewrite of Eq. (feq-full) that keeps FP32 rounding relative to the
+// small deviations instead of to f ~ w.
+template <int SCHEME, typename C>
+__device__ __forceinline__ void collide(C d[9], const Coef<C>& k)
+{
+    const C drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
+    const C jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
+    const C jy = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
+    const C inv = C(1) / (C(1) + drho);
+    const C ux = jx * inv, uy = jy * inv;
+    const C base = drho - C(1.5) * (jx * ux + jy * uy);
+
+    C q[9];
+    q[0] = W<C>::rest * base;
+    {
+        const C s = W<C>::axis * (base + C(4.5) * jx * ux), t = W<C>::axis * C(3) * jx;
+        q[1] = s + t;
+        q[3] = s - t;
+    }
+    {
+        const C s = W<C>::axis * (base + C(4.5) * jy * uy), t = W<C>::axis * C(3) * jy;
+        q[2] = s + t;
+        q[4] = s - t;
+    }
+    {
+        const C ej = jx + jy, eu = ux + uy;
+        const C s = W<C>::diag * (base + C(4.5) * ej * eu), t = W<C>::diag * C(3) * ej;
+        q[5] = s + t;
+        q[7] = s - t;
+    }
+    {
+        const C ej = jy - jx, eu = uy - ux;
+        const C s = W<C>::diag * (base + C(4.5) * ej * eu), t = W<C>::diag * C(3) * ej;
+        q[6] = s + t;
+        q[8] = s - t;
+    }
+
+    if constexpr (SCHEME == SRT) {
+        // Eq. (lb.srt): f* = f - (f - f^eq)/tau
+#pragma unroll
+        for (int a = 0; a < 9; ++a) d[a] = d[a] + k.omega * (q[a] - d[a]);
+    } else {
+        // Group sums of Eq. (sigma1-2-0): C_1 over the axis links, C_2 over the
+        // diagonal links, each sum_k (-1)^k (f_k - f^eq_k) / 4.
+        const C c1 = C(0.25) * (((d[2] - q[2]) + (d[4] - q[4])) - ((d[1] - q[1]) + (d[3] - q[3])));
+        const C c2 = C(0.25) * (((d[6] - q[6]) + (d[8] - q[8])) - ((d[5] - q[5]) + (d[7] - q[7])));
+        if constexpr (SCHEME == SMRT) {
+            // Eq. (SmrtLBM-1): f*_a = f^eq_a + (-1)^a (1 - 1/tau) C_g(a)
+            const C g1 = k.a * c1, g2 = k.a * c2;
+            d[0] = q[0];
+            d[1] = q[1] - g1;
+            d[2] = q[2] + g1;
+            d[3] = q[3] - g1;
+            d[4] = q[4] + g1;
+            d[5] = q[5] - g2;
+            d[6] = q[6] + g2;
+            d[7] = q[7] - g2;
+            d[8] = q[8] + g2;
+        } else {
+            // Eq. (SmrtLBM-lb.1.5): f*_a = f_a - (f_a - f^eq_a)/tau_s + (-1)^a (1/tau_s - 1/tau) C_g(a)
+            const C g1 = k.b * c1, g2 = k.b * c2;
+#pragma unroll
+            for (int a = 0; a < 9; ++a) d[a] = d[a] + k.omega_s * (q[a] - d[a]);
+            d[1] -= g1;
+            d[2] += g1;
+            d[3] -= g1;
+            d[4] += g1;
+            d[5] -= g2;
+            d[6] += g2;
+            d[7] -= g2;
+            d[8] += g2;
+        }
+    }
+}
+
+// Pull of the nine incoming populations of an interior node: every source
+// x - e_a lies inside the lattice.
+template <typename T>
+__device__ __forceinline__ void gather_interior(const T* __restrict__ src, const Geom& g, int x, int y,
+                                                typename Storage<T>::C d[9])
+{
+    using S = Storage<T>;
+    const T* p = src + (int64_t)y * g.pitch + x;
+    const int64_t P = g.plane, R = g.pitch;
+    d[0] = S::load(p);
+    d[1] = S::load(p + 1 * P - 1);
+    d[2] = S::load(p + 2 * P - R);
+    d[3] = S::load(p + 3 * P + 1);
+    d[4] = S::load(p + 4 * P + R);
+    d[5] = S::load(p + 5 * P - R - 1);
+    d[6] = S::load(p + 6 * P - R + 1);
+    d[7] = S::load(p + 7 * P + R + 1);
+    d[8] = S::load(p + 8 * P + R - 1);
+}
+
+// Pull at a node on the outer ring.  Periodic: sources wrap around.  Cavity:
+// a source beyond a wall is replaced by the node's own opposite population
+// (half-way bounce-back); a link from the lid row (y = ny, corners included)
+// gains 6 w_a (e_a . u_lid), which is -u_lid/6 for a = 7, +u_lid/6 for a = 8
+// and 0 for a = 4.
+template <typename T, int BC>
+__device__ __forceinline__ void gather_edge(const T* __restrict__ src, const Geom& g, int x, int y,
+                                            typename Storage<T>::C d[9], typename Storage<T>::C lid)
+{
+    using S = Storage<T>;
+    using C = typename Storage<T>::C;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        int sx = x - EX[a], sy = y - EY[a];
+        if constexpr (BC == PERIODIC) {
+            sx = sx < 0 ? sx + g.nx : (sx >= g.nx ? sx - g.nx : sx);
+            sy = sy < 0 ? sy + g.ny : (sy >= g.ny ? sy - g.ny : sy);
+            d[a] = S::load(src + a * g.plane + (int64_t)sy * g.pitch + sx);
+        } else {
+            if (sx >= 0 && sx < g.nx && sy >= 0 && sy < g.ny) {
+                d[a] = S::load(src + a * g.plane + (int64_t)sy * g.pitch + sx);
+            } else {
+                C v = S::load(src + OPP[a] * g.plane + (int64_t)y * g.pitch + x);
+                if (sy == g.ny) v += C(EX[a]) * lid;  // a = 7: -lid, a = 8: +lid, a = 4: 0
+                d[a] = v;
+            }
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void scatter_store(T* __restrict__ dst, const Geom& g, int x, int y,
+                                              const typename Storage<T>::C d[9])
+{
+    T* p = dst + (int64_t)y * g.pitch + x;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) Storage<T>::store(p + a * g.plane, d[a]);
+}
+
+// One time step.  Block (bx, by) threads; each thread updates `rows` nodes
+// spaced by by along y, so a block covers a bx x (by * rows) tile.
+template <typename T, int SCHEME, int BC>
+__global__ void __launch_bounds__(1024) stream_collide(const T* __restrict__ src, T* __restrict__ dst,
+                                                       Geom g, Coef<typename Storage<T>::C> k)
+{
+    using C = typename Storage<T>::C;
+    const int tile = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int tx = tile % g.tiles_x, ty = tile / g.tiles_x;
+    const int x = tx * g.bx + threadIdx.x;
+    if (x >= g.nx) return;
+    const int y0 = ty * g.by * g.rows + threadIdx.y;
+    for (int r = 0; r < g.rows; ++r) {
+        const int y = y0 + r * g.by;
+        if (y >= g.ny) break;
+        C d[9];
+        const bool edge = (x == 0) | (x == g.nx - 1) | (y == 0) | (y == g.ny - 1);
+        if (edge)
+            gather_edge<T, BC>(src, g, x, y, d, k.lid);
+        else
+            gather_interior<T>(src, g, x, y, d);
+        collide<SCHEME>(d, k);
+        scatter_store<T>(dst, g, x, y, d);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Initialisation, export and reductions (off the per-step path).
+
+// d_a = f^eq_a(rho, u) - w_a in FP64, rounded once to the storage type.
+template <typename T, typename F>
+__global__ void init_equilibrium(T* __restrict__ dst, Geom g, const F* __restrict__ rho,
+                                 const F* __restrict__ ux, const F* __restrict__ uy)
+{
+    const int64_t n = (int64_t)g.nx * g.ny;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int y = (int)(i / g.nx), x = (int)(i % g.nx);
+        const double r = rho ? (double)rho[i] : 1.0;
+        const double vx = ux ? (double)ux[i] : 0.0, vy = uy ? (double)uy[i] : 0.0;
+        const double uu = vx * vx + vy * vy;
+        T* p = dst + (int64_t)y * g.pitch + x;
+        for (int a = 0; a < 9; ++a) {
+            const double eu = EX[a] * vx + EY[a] * vy;
+            const double dev = weight_f64(a) * ((r - 1.0) + r * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
+            Storage<T>::from_f64(p + a * g.plane, dev);
+        }
+    }
+}
+
+// State <-> dense full populations f = w + d, layout [9][ny][nx].
+template <typename T, typename F>
+__global__ void set_populations(T* __restrict__ dst, Geom g, const F* __restrict__ f)
+{
+    const int64_t n = (int64_t)g.nx * g.ny;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int y = (int)(i / g.nx), x = (int)(i % g.nx);
+        for (int a = 0; a < 9; ++a)
+            Storage<T>::from_f64(dst + a * g.plane + (int64_t)y * g.pitch + x,
+                                 (double)f[a * n + i] - weight_f64(a));
+    }
+}
+
+template <typename T, typename F>
+__global__ void get_populations(const T* __restrict__ src, Geom g, F* __restrict__ f)
+{
+    const int64_t n = (int64_t)g.nx * g.ny;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int y = (int)(i / g.nx), x = (int)(i % g.nx);
+        for (int a = 0; a < 9; ++a)
+            f[a * n + i] = (F)(weight_f64(a) + Storage<T>::to_f64(src + a * g.plane + (int64_t)y * g.pitch + x));
+    }
+}
+
+// Density deviation and momentum of a stored node, in FP64.
+template <typename T>
+__device__ __forceinline__ void node_moments_f64(const T* __restrict__ src, const Geom& g, int64_t off,
+                                                 double& drho, double& jx, double& jy)
+{
+    double d[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) d[a] = Storage<T>::to_f64(src + a * g.plane + off);
+    drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
+    jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
+    jy = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
+}
+
+// rho, ux, uy of the stored state (Eq. fea-0) into dense [ny][nx] arrays.
+template <typename T, typename F>
+__global__ void export_moments(const T* __restrict__ src, Geom g, F* __restrict__ rho,
+                               F* __restrict__ ux, F* __restrict__ uy)
+{
+    const int64_t n = (int64_t)g.nx * g.ny;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int y = (int)(i / g.nx), x = (int)(i % g.nx);
+        double drho, jx, jy;
+        node_moments_f64(src, g, (int64_t)y * g.pitch + x, drho, jx, jy);
+        const double r = 1.0 + drho;
+        if (rho) rho[i] = (F)r;
+        if (ux) ux[i] = (F)(jx / r);
+        if (uy) uy[i] = (F)(jy / r);
+    }
+}
+
+// Sum over a 64-wide wavefront with xor shuffles (fixed pairing order).
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+constexpr int RED_THREADS = 256;
+constexpr int RED_WAVES = RED_THREADS / 64;
+constexpr int RED_VALUES = 4; // sum |u - u_snap|^2, sum |u|^2, sum (rho - 1), non-finite nodes
+
+// Per-block FP64 partial sums for the residual and the mass.  Each thread
+// walks a fixed, grid-strided set of nodes; lanes combine by xor shuffles and
+// waves in index order, so the result does not depend on timing.  With
+// `update` set, the node's velocity replaces the snapshot.
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS) reduce_partials(const T* __restrict__ src, Geom g,
+                                                               double* __restrict__ snap_ux,
+                                                               double* __restrict__ snap_uy, int update,
+                                                               double* __restrict__ partials)
+{
+    __shared__ double lds[RED_VALUES][RED_WAVES];
+    const int64_t n = (int64_t)g.nx * g.ny;
+    double s[RED_VALUES] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * RED_THREADS) {
+        const int y = (int)(i / g.nx), x = (int)(i % g.nx);
+        double drho, jx, jy;
+        node_moments_f64(src, g, (int64_t)y * g.pitch + x, drho, jx, jy);
+        const double r = 1.0 + drho;
+        const double vx = jx / r, vy = jy / r;
+        const double ox = snap_ux[i], oy = snap_uy[i];
+        const double dx = vx - ox, dy = vy - oy;
+        s[0] += dx * dx + dy * dy;
+        s[1] += vx * vx + vy * vy;
+        s[2] += drho;
+        s[3] += (__builtin_isfinite(r) && __builtin_isfinite(vx) && __builtin_isfinite(vy)) ? 0.0 : 1.0;
+        if (update) {
+            snap_ux[i] = vx;
+            snap_uy[i] = vy;
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int v = 0; v < RED_VALUES; ++v) {
+        const double t = wave_sum(s[v]);
+        if (lane == 0) lds[v][wave] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < RED_VALUES) {
+        double t = 0.0;
+        for (int w = 0; w < RED_WAVES; ++w) t += lds[threadIdx.x][w];
+        partials[(int64_t)blockIdx.x * RED_VALUES + threadIdx.x] = t;
+    }
+}
+
+// One block: sums `nparts` partial rows in a fixed order into out[0..3].
+__global__ void __launch_bounds__(RED_THREADS) reduce_finish(const double* __restrict__ partials,
+                                                             int nparts, double* __restrict__ out)
+{
+    __shared__ double lds[RED_VALUES][RED_WAVES];
+    double s[RED_VALUES] = {0.0, 0.0, 0.0, 0.0};
+    for (int p = threadIdx.x; p < nparts; p += RED_THREADS)
+#pragma unroll
+        for (int v = 0; v < RED_VALUES; ++v) s[v] += partials[(int64_t)p * RED_VALUES + v];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int v = 0; v < RED_VALUES; ++v) {
+        const double t = wave_sum(s[v]);
+        if (lane == 0) lds[v][wave] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < RED_VALUES) {
+        double t = 0.0;
+        for (int w = 0; w < RED_WAVES; ++w) t += lds[threadIdx.x][w];
+        out[threadIdx.x] = t;
+    }
+}
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Plain streaming copy, 16 bytes per lane per iteration.
+__global__ void __launch_bounds__(256) copy_kernel(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
+                                                   int64_t n16)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n16;
+         i += (int64_t)gridDim.x * blockDim.x)
+        __builtin_nontemporal_store(src[i], dst + i);
+}
+
+} // namespace smrt

@@ -1,0 +1,521 @@
+// smrt_api.hip -- host runtime and C ABI (include/smrt.h) of the gfx950 D2Q9
+// SRT / SmrtLBM library: parameter checks, workspace layout, kernel dispatch,
+// residual and mass read-back.
+#include "smrt.h"
+
+#include "lbm_kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(SMRT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(call)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);                                          \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+size_t elem_bytes(int storage)
+{
+    switch (storage) {
+    case SMRT_F64: return 8;
+    case SMRT_F32: return 4;
+    case SMRT_F16:
+    case SMRT_BF16: return 2;
+    default: return 0;
+    }
+}
+
+// Byte offsets of everything the context keeps in its device workspace.
+struct Layout {
+    int pitch = 0;       // elements per row; rows start on 256-byte boundaries
+    int64_t plane = 0;   // elements per direction plane
+    size_t buffer = 0;   // bytes of one population buffer (9 planes)
+    size_t off_a = 0, off_b = 0, off_snap_x = 0, off_snap_y = 0, off_partials = 0, off_result = 0;
+    size_t total = 0;
+    int red_blocks = 0;
+};
+
+// Extra bytes between direction planes, so that the nine planes of a
+// power-of-two lattice do not start on the same HBM channel.
+size_t plane_pad_bytes()
+{
+    const char* s = std::getenv("SMRT_PLANE_PAD_BYTES");
+    if (s && *s) return round_up((size_t)std::strtoull(s, nullptr, 10), kAlign);
+    return 4096;
+}
+
+Layout make_layout(int nx, int ny, int storage)
+{
+    Layout L;
+    const size_t e = elem_bytes(storage);
+    L.pitch = (int)round_up((size_t)nx, kAlign / e);
+    const size_t plane_bytes = round_up((size_t)L.pitch * ny * e, 65536) + plane_pad_bytes();
+    L.plane = (int64_t)(plane_bytes / e);
+    L.buffer = 9 * plane_bytes;
+    const size_t n = (size_t)nx * ny;
+    L.red_blocks = (int)std::min<size_t>((n + smrt::RED_THREADS - 1) / smrt::RED_THREADS, 2048);
+    size_t off = 0;
+    L.off_a = off;
+    off += round_up(L.buffer, kAlign);
+    L.off_b = off;
+    off += round_up(L.buffer, kAlign);
+    L.off_snap_x = off;
+    off += round_up(n * sizeof(double), kAlign);
+    L.off_snap_y = off;
+    off += round_up(n * sizeof(double), kAlign);
+    L.off_partials = off;
+    off += round_up((size_t)L.red_blocks * smrt::RED_VALUES * sizeof(double), kAlign);
+    L.off_result = off;
+    off += kAlign;
+    L.total = off;
+    return L;
+}
+
+int check_params(const smrt_params* p, double* tau_out)
+{
+    if (!p) return fail(SMRT_EINVAL, "params is NULL");
+    if (p->nx < 3 || p->ny < 3) return fail(SMRT_EINVAL, "nx and ny must be >= 3 (got %d x %d)", p->nx, p->ny);
+    if ((int64_t)p->nx * p->ny > (int64_t)1 << 34)
+        return fail(SMRT_EINVAL, "lattice of %d x %d nodes is too large", p->nx, p->ny);
+    if (p->scheme < SMRT_SCHEME_SRT || p->scheme > SMRT_SCHEME_TRT)
+        return fail(SMRT_EINVAL, "unknown scheme %d", p->scheme);
+    if (p->boundary != SMRT_CAVITY && p->boundary != SMRT_PERIODIC)
+        return fail(SMRT_EINVAL, "unknown boundary %d", p->boundary);
+    if (elem_bytes(p->storage) == 0) return fail(SMRT_EINVAL, "unknown storage type %d", p->storage);
+    if (p->reserved0 != 0) return fail(SMRT_EINVAL, "reserved0 must be 0");
+    for (int i = 0; i < 4; ++i)
+        if (p->reserved[i] != 0) return fail(SMRT_EINVAL, "reserved[%d] must be 0", i);
+    if (!std::isfinite(p->u_lid) || std::fabs(p->u_lid) >= 1.0 / std::sqrt(3.0))
+        return fail(SMRT_EINVAL, "|u_lid| must be below the lattice sound speed 1/sqrt(3) (got %g)", p->u_lid);
+    double tau = p->tau;
+    if (!(tau > 0.0)) {
+        // Re = U N / nu and nu = (2 tau - 1)/6 (Eq. relation-chapman-viscosity, e = dx = 1)
+        if (!(p->re > 0.0) || !std::isfinite(p->re))
+            return fail(SMRT_EINVAL, "tau <= 0 needs a positive Reynolds number (got re = %g)", p->re);
+        if (!(std::fabs(p->u_lid) > 0.0))
+            return fail(SMRT_EINVAL, "deriving tau from re needs a non-zero lid speed");
+        tau = 3.0 * std::fabs(p->u_lid) * (double)p->nx / p->re + 0.5;
+    }
+    if (!(tau > 0.5) || !std::isfinite(tau))
+        return fail(SMRT_EINVAL, "relaxation time must exceed 1/2 (got %.17g)", tau);
+    if (p->scheme == SMRT_SCHEME_TRT && (!(p->tau_s > 0.5) || !std::isfinite(p->tau_s)))
+        return fail(SMRT_EINVAL, "TRT needs tau_s > 1/2 (got %g)", p->tau_s);
+    *tau_out = tau;
+    return SMRT_OK;
+}
+
+} // namespace
+
+struct smrt_ctx {
+    smrt_params p{};
+    double tau = 0.0;
+    hipStream_t stream = nullptr;
+    Layout L;
+    char* ws = nullptr;
+    bool owns_ws = false;
+    double* host_result = nullptr; // pinned, RED_VALUES doubles
+    int cur = 0;                   // 0: state in buffer A, 1: in buffer B
+    int64_t steps = 0, snap_step = 0;
+    int bx = 256, by = 1, rows = 1;
+
+    void* buffer(int which) const { return ws + (which == 0 ? L.off_a : L.off_b); }
+    double* snap_x() const { return reinterpret_cast<double*>(ws + L.off_snap_x); }
+    double* snap_y() const { return reinterpret_cast<double*>(ws + L.off_snap_y); }
+    double* partials() const { return reinterpret_cast<double*>(ws + L.off_partials); }
+    double* result() const { return reinterpret_cast<double*>(ws + L.off_result); }
+
+    smrt::Geom geom() const
+    {
+        smrt::Geom g;
+        g.nx = p.nx;
+        g.ny = p.ny;
+        g.pitch = L.pitch;
+        g.plane = L.plane;
+        g.bx = bx;
+        g.by = by;
+        g.rows = rows;
+        g.tiles_x = (p.nx + bx - 1) / bx;
+        return g;
+    }
+    int64_t nodes() const { return (int64_t)p.nx * p.ny; }
+};
+
+namespace {
+
+int elementwise_blocks(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 65536); }
+
+template <typename T> int launch_step(smrt_ctx* c, const void* src, void* dst)
+{
+    using C = typename smrt::Storage<T>::C;
+    const smrt::Geom g = c->geom();
+    smrt::Coef<C> k;
+    const double omega = 1.0 / c->tau;
+    const double omega_s = c->p.scheme == SMRT_SCHEME_TRT ? 1.0 / c->p.tau_s : 1.0;
+    k.omega = (C)omega;
+    k.omega_s = (C)omega_s;
+    k.a = (C)(1.0 - omega);
+    k.b = (C)(omega_s - omega);
+    k.lid = (C)(c->p.boundary == SMRT_CAVITY ? c->p.u_lid / 6.0 : 0.0);
+    const int tiles_y = (g.ny + g.by * g.rows - 1) / (g.by * g.rows);
+    const int64_t blocks = (int64_t)g.tiles_x * tiles_y;
+    if (blocks > std::numeric_limits<int>::max()) return fail(SMRT_EINVAL, "grid too large");
+    dim3 grid((unsigned)blocks), block(g.bx, g.by);
+    const T* s = static_cast<const T*>(src);
+    T* d = static_cast<T*>(dst);
+    const bool per = c->p.boundary == SMRT_PERIODIC;
+    switch (c->p.scheme) {
+    case SMRT_SCHEME_SRT:
+        if (per) smrt::stream_collide<T, smrt::SRT, smrt::PERIODIC><<<grid, block, 0, c->stream>>>(s, d, g, k);
+        else smrt::stream_collide<T, smrt::SRT, smrt::CAVITY><<<grid, block, 0, c->stream>>>(s, d, g, k);
+        break;
+    case SMRT_SCHEME_SMRT:
+        if (per) smrt::stream_collide<T, smrt::SMRT, smrt::PERIODIC><<<grid, block, 0, c->stream>>>(s, d, g, k);
+        else smrt::stream_collide<T, smrt::SMRT, smrt::CAVITY><<<grid, block, 0, c->stream>>>(s, d, g, k);
+        break;
+    default:
+        if (per) smrt::stream_collide<T, smrt::TRT, smrt::PERIODIC><<<grid, block, 0, c->stream>>>(s, d, g, k);
+        else smrt::stream_collide<T, smrt::TRT, smrt::CAVITY><<<grid, block, 0, c->stream>>>(s, d, g, k);
+        break;
+    }
+    return SMRT_OK;
+}
+
+int dispatch_step(smrt_ctx* c, const void* src, void* dst)
+{
+    switch (c->p.storage) {
+    case SMRT_F64: return launch_step<double>(c, src, dst);
+    case SMRT_F32: return launch_step<float>(c, src, dst);
+    case SMRT_F16: return launch_step<_Float16>(c, src, dst);
+    default: return launch_step<smrt::bf16>(c, src, dst);
+    }
+}
+
+// Calls fn(T*) with the state buffer typed by the storage type.
+template <typename Fn> int with_storage(smrt_ctx* c, void* buf, Fn&& fn)
+{
+    switch (c->p.storage) {
+    case SMRT_F64: fn(static_cast<double*>(buf)); break;
+    case SMRT_F32: fn(static_cast<float*>(buf)); break;
+    case SMRT_F16: fn(static_cast<_Float16*>(buf)); break;
+    default: fn(static_cast<smrt::bf16*>(buf)); break;
+    }
+    return SMRT_OK;
+}
+
+int check_io_dtype(int32_t dtype)
+{
+    if (dtype != SMRT_F32 && dtype != SMRT_F64)
+        return fail(SMRT_EINVAL, "field dtype must be SMRT_F32 or SMRT_F64 (got %d)", dtype);
+    return SMRT_OK;
+}
+
+int after_launch(const char* what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, what);
+    return SMRT_OK;
+}
+
+// Launches the partial sums (optionally refreshing the snapshot) and the
+// finisher; copies the RED_VALUES sums to the pinned host buffer and waits.
+int run_reduction(smrt_ctx* c, int update)
+{
+    const smrt::Geom g = c->geom();
+    void* state = c->buffer(c->cur);
+    with_storage(c, state, [&](auto* s) {
+        smrt::reduce_partials<<<c->L.red_blocks, smrt::RED_THREADS, 0, c->stream>>>(
+            s, g, c->snap_x(), c->snap_y(), update, c->partials());
+    });
+    smrt::reduce_finish<<<1, smrt::RED_THREADS, 0, c->stream>>>(c->partials(), c->L.red_blocks, c->result());
+    int rc = after_launch("reduction kernels");
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(c->host_result, c->result(), smrt::RED_VALUES * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SMRT_OK;
+}
+
+// Snapshot := current velocity, without a host round trip.
+int refresh_snapshot(smrt_ctx* c)
+{
+    const smrt::Geom g = c->geom();
+    with_storage(c, c->buffer(c->cur), [&](auto* s) {
+        smrt::reduce_partials<<<c->L.red_blocks, smrt::RED_THREADS, 0, c->stream>>>(
+            s, g, c->snap_x(), c->snap_y(), 1, c->partials());
+    });
+    c->steps = 0;
+    c->snap_step = 0;
+    return after_launch("snapshot refresh");
+}
+
+template <typename F> int init_fields_typed(smrt_ctx* c, const void* rho, const void* ux, const void* uy)
+{
+    const smrt::Geom g = c->geom();
+    with_storage(c, c->buffer(c->cur), [&](auto* s) {
+        smrt::init_equilibrium<<<elementwise_blocks(c->nodes()), 256, 0, c->stream>>>(
+            s, g, static_cast<const F*>(rho), static_cast<const F*>(ux), static_cast<const F*>(uy));
+    });
+    return after_launch("init_equilibrium");
+}
+
+} // namespace
+
+extern "C" {
+
+size_t smrt_workspace_bytes(const smrt_params* p)
+{
+    double tau;
+    if (check_params(p, &tau) != SMRT_OK) return 0;
+    return make_layout(p->nx, p->ny, p->storage).total;
+}
+
+int smrt_create(const smrt_params* p, void* dev_ws, size_t ws_bytes, smrt_ctx** out)
+{
+    try {
+        if (!out) return fail(SMRT_EINVAL, "out is NULL");
+        *out = nullptr;
+        double tau;
+        int rc = check_params(p, &tau);
+        if (rc) return rc;
+        Layout L = make_layout(p->nx, p->ny, p->storage);
+        if (dev_ws && ws_bytes < L.total)
+            return fail(SMRT_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, L.total);
+        if (dev_ws && (reinterpret_cast<uintptr_t>(dev_ws) % kAlign))
+            return fail(SMRT_EINVAL, "workspace must be %zu-byte aligned", kAlign);
+        smrt_ctx* c = new (std::nothrow) smrt_ctx;
+        if (!c) return fail(SMRT_ENOMEM, "out of host memory");
+        c->p = *p;
+        c->tau = tau;
+        c->stream = static_cast<hipStream_t>(p->stream);
+        c->L = L;
+        if (p->nx >= 256) {
+            c->bx = 256; c->by = 1;
+        } else if (p->nx >= 128) {
+            c->bx = 128; c->by = 2;
+        } else {
+            c->bx = 64; c->by = 4;
+        }
+        hipError_t e;
+        if (dev_ws) {
+            c->ws = static_cast<char*>(dev_ws);
+        } else {
+            e = hipMalloc(reinterpret_cast<void**>(&c->ws), L.total);
+            if (e != hipSuccess) {
+                delete c;
+                return fail(SMRT_ENOMEM, "hipMalloc(%zu): %s", L.total, hipGetErrorString(e));
+            }
+            c->owns_ws = true;
+        }
+        e = hipHostMalloc(reinterpret_cast<void**>(&c->host_result), smrt::RED_VALUES * sizeof(double),
+                          hipHostMallocDefault);
+        if (e != hipSuccess) {
+            smrt_destroy(c);
+            return fail(SMRT_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
+        }
+        rc = init_fields_typed<float>(c, nullptr, nullptr, nullptr);
+        if (!rc) rc = refresh_snapshot(c);
+        if (rc) {
+            smrt_destroy(c);
+            return rc;
+        }
+        *out = c;
+        return SMRT_OK;
+    } catch (...) {
+        return fail(SMRT_ENOMEM, "unexpected host exception in smrt_create");
+    }
+}
+
+int smrt_init_fields(smrt_ctx* c, const void* rho, const void* ux, const void* uy, int32_t dtype)
+{
+    if (!c) return fail(SMRT_EINVAL, "context is NULL");
+    int rc = check_io_dtype(dtype);
+    if (rc) return rc;
+    rc = dtype == SMRT_F64 ? init_fields_typed<double>(c, rho, ux, uy) : init_fields_typed<float>(c, rho, ux, uy);
+    if (rc) return rc;
+    return refresh_snapshot(c);
+}
+
+int smrt_set_populations(smrt_ctx* c, const void* f, int32_t dtype)
+{
+    if (!c) return fail(SMRT_EINVAL, "context is NULL");
+    if (!f) return fail(SMRT_EINVAL, "populations pointer is NULL");
+    int rc = check_io_dtype(dtype);
+    if (rc) return rc;
+    const smrt::Geom g = c->geom();
+    const int blocks = elementwise_blocks(c->nodes());
+    with_storage(c, c->buffer(c->cur), [&](auto* s) {
+        if (dtype == SMRT_F64)
+            smrt::set_populations<<<blocks, 256, 0, c->stream>>>(s, g, static_cast<const double*>(f));
+        else
+            smrt::set_populations<<<blocks, 256, 0, c->stream>>>(s, g, static_cast<const float*>(f));
+    });
+    rc = after_launch("set_populations");
+    if (rc) return rc;
+    return refresh_snapshot(c);
+}
+
+int smrt_get_populations(smrt_ctx* c, void* f, int32_t dtype)
+{
+    if (!c) return fail(SMRT_EINVAL, "context is NULL");
+    if (!f) return fail(SMRT_EINVAL, "populations pointer is NULL");
+    int rc = check_io_dtype(dtype);
+    if (rc) return rc;
+    const smrt::Geom g = c->geom();
+    const int blocks = elementwise_blocks(c->nodes());
+    with_storage(c, c->buffer(c->cur), [&](auto* s) {
+        if (dtype == SMRT_F64)
+            smrt::get_populations<<<blocks, 256, 0, c->stream>>>(s, g, static_cast<double*>(f));
+        else
+            smrt::get_populations<<<blocks, 256, 0, c->stream>>>(s, g, static_cast<float*>(f));
+    });
+    return after_launch("get_populations");
+}
+
+int smrt_step(smrt_ctx* c, int64_t n)
+{
+    if (!c) return fail(SMRT_EINVAL, "context is NULL");
+    if (n < 0) return fail(SMRT_EINVAL, "step count must be >= 0 (got %lld)", (long long)n);
+    for (int64_t i = 0; i < n; ++i) {
+        int rc = dispatch_step(c, c->buffer(c->cur), c->buffer(c->cur ^ 1));
+        if (rc) return rc;
+        c->cur ^= 1;
+        c->steps += 1;
+    }
+    return n ? after_launch("stream_collide") : SMRT_OK;
+}
+
+int smrt_moments(smrt_ctx* c, void* rho, void* ux, void* uy, int32_t dtype)
+{
+    if (!c) return fail(SMRT_EINVAL, "context is NULL");
+    int rc = check_io_dtype(dtype);
+    if (rc) return rc;
+    if (!rho && !ux && !uy) return SMRT_OK;
+    const smrt::Geom g = c->geom();
+    const int blocks = elementwise_blocks(c->nodes());
+    with_storage(c, c->buffer(c->cur), [&](auto* s) {
+        if (dtype == SMRT_F64)
+            smrt::export_moments<<<blocks, 256, 0, c->stream>>>(s, g, static_cast<double*>(rho),
+                                                                static_cast<double*>(ux), static_cast<double*>(uy));
+        else
+            smrt::export_moments<<<blocks, 256, 0, c->stream>>>(s, g, static_cast<float*>(rho),
+                                                                static_cast<float*>(ux), static_cast<float*>(uy));
+    });
+    return after_launch("export_moments");
+}
+
+int smrt_residual(smrt_ctx* c, double* out)
+{
+    if (!c || !out) return fail(SMRT_EINVAL, "context or output is NULL");
+    const int64_t window = c->steps - c->snap_step;
+    if (window <= 0) return fail(SMRT_ESTATE, "no step since the last residual snapshot");
+    int rc = run_reduction(c, 1);
+    if (rc) return rc;
+    c->snap_step = c->steps;
+    const double du2 = c->host_result[0], u2 = c->host_result[1], bad = c->host_result[3];
+    if (bad != 0.0 || !std::isfinite(du2) || !std::isfinite(u2)) {
+        *out = std::numeric_limits<double>::quiet_NaN();
+        return fail(SMRT_EUNSTABLE, "%.0f nodes hold a non-finite density or velocity", bad);
+    }
+    if (u2 == 0.0)
+        *out = du2 == 0.0 ? 0.0 : std::numeric_limits<double>::infinity();
+    else
+        *out = std::sqrt(du2) / ((double)window * std::sqrt(u2));
+    return SMRT_OK;
+}
+
+int smrt_mass(smrt_ctx* c, double* out)
+{
+    if (!c || !out) return fail(SMRT_EINVAL, "context or output is NULL");
+    int rc = run_reduction(c, 0);
+    if (rc) return rc;
+    const double drho = c->host_result[2], bad = c->host_result[3];
+    if (bad != 0.0 || !std::isfinite(drho)) {
+        *out = std::numeric_limits<double>::quiet_NaN();
+        return fail(SMRT_EUNSTABLE, "%.0f nodes hold a non-finite density or velocity", bad);
+    }
+    *out = (double)c->nodes() + drho;
+    return SMRT_OK;
+}
+
+int64_t smrt_steps_done(const smrt_ctx* c) { return c ? c->steps : -1; }
+
+double smrt_tau(const smrt_ctx* c) { return c ? c->tau : std::numeric_limits<double>::quiet_NaN(); }
+
+int smrt_set_launch(smrt_ctx* c, int32_t bx, int32_t by, int32_t rows)
+{
+    if (!c) return fail(SMRT_EINVAL, "context is NULL");
+    const int threads = bx * by;
+    if (bx < 16 || bx % 16 || by < 1 || (threads != 64 && threads != 128 && threads != 256 && threads != 512 &&
+                                          threads != 1024))
+        return fail(SMRT_EINVAL, "invalid block shape %d x %d", bx, by);
+    if (rows < 1 || rows > 8) return fail(SMRT_EINVAL, "rows per thread must be in 1..8 (got %d)", rows);
+    c->bx = bx;
+    c->by = by;
+    c->rows = rows;
+    return SMRT_OK;
+}
+
+int smrt_synchronize(smrt_ctx* c)
+{
+    if (!c) return fail(SMRT_EINVAL, "context is NULL");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SMRT_OK;
+}
+
+void smrt_destroy(smrt_ctx* c)
+{
+    if (!c) return;
+    if (c->host_result) (void)hipHostFree(c->host_result);
+    if (c->owns_ws && c->ws) (void)hipFree(c->ws);
+    delete c;
+}
+
+const char* smrt_last_error(void) { return g_error.c_str(); }
+
+int smrt_copy_kernel(const void* src, void* dst, size_t bytes, void* stream)
+{
+    if (!src || !dst) return fail(SMRT_EINVAL, "copy pointers must not be NULL");
+    if (bytes % 16 || reinterpret_cast<uintptr_t>(src) % 16 || reinterpret_cast<uintptr_t>(dst) % 16)
+        return fail(SMRT_EINVAL, "copy size and pointers must be multiples of 16 bytes");
+    const int64_t n16 = (int64_t)(bytes / 16);
+    if (n16 == 0) return SMRT_OK;
+    const int blocks = (int)std::min<int64_t>((n16 + 255) / 256, 256 * 64);
+    smrt::copy_kernel<<<blocks, 256, 0, static_cast<hipStream_t>(stream)>>>(
+        static_cast<const smrt::u32x4*>(src), static_cast<smrt::u32x4*>(dst), n16);
+    return after_launch("copy_kernel");
+}
+
+} // extern "C"

@@ -1,0 +1,241 @@
+"""Python binding of the gfx950 D2Q9 SRT / SmrtLBM library (``include/smrt.h``).
+
+Argument marshalling only: every step of the lattice update runs in the HIP
+kernels of ``libsmrt.so``.  PyTorch provides device memory (the workspace and
+the field/population tensors) and the stream.  There is no CPU fallback: on a
+machine without the built library or without a GPU, creating a solver raises.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsmrt.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
+SCHEMES = {"srt": 0, "smrt": 1, "trt": 2}
+BOUNDARIES = {"cavity": 0, "periodic": 1}
+STORAGE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
+_IO_DTYPES = {torch.float64: 0, torch.float32: 1}
+
+EXPORTED = (
+    "smrt_workspace_bytes", "smrt_create", "smrt_init_fields", "smrt_set_populations",
+    "smrt_get_populations", "smrt_step", "smrt_moments", "smrt_residual", "smrt_mass",
+    "smrt_steps_done", "smrt_tau", "smrt_set_launch", "smrt_synchronize", "smrt_destroy",
+    "smrt_last_error", "smrt_copy_kernel",
+)
+
+
+class SmrtError(RuntimeError):
+    """A negative status returned by the library."""
+
+    def __init__(self, code, message):
+        super().__init__("%s (status %d)" % (message, code))
+        self.code = code
+
+
+class UnstableError(SmrtError):
+    """The lattice holds a non-finite density or velocity."""
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("scheme", ctypes.c_int32), ("boundary", ctypes.c_int32),
+        ("storage", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("tau", ctypes.c_double), ("re", ctypes.c_double),
+        ("u_lid", ctypes.c_double), ("tau_s", ctypes.c_double),
+        ("stream", ctypes.c_void_p),
+        ("reserved", ctypes.c_int64 * 4),
+    ]
+
+
+_lib = None
+
+
+def load():
+    """Loads libsmrt.so (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("HIP library %s is not built; run __graft_entry__.build()" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+    pp = ctypes.POINTER(Params)
+    sig = {
+        "smrt_workspace_bytes": (ctypes.c_size_t, [pp]),
+        "smrt_create": (ctypes.c_int, [pp, vp, ctypes.c_size_t, ctypes.POINTER(vp)]),
+        "smrt_init_fields": (ctypes.c_int, [vp, vp, vp, vp, i32]),
+        "smrt_set_populations": (ctypes.c_int, [vp, vp, i32]),
+        "smrt_get_populations": (ctypes.c_int, [vp, vp, i32]),
+        "smrt_step": (ctypes.c_int, [vp, i64]),
+        "smrt_moments": (ctypes.c_int, [vp, vp, vp, vp, i32]),
+        "smrt_residual": (ctypes.c_int, [vp, dp]),
+        "smrt_mass": (ctypes.c_int, [vp, dp]),
+        "smrt_steps_done": (i64, [vp]),
+        "smrt_tau": (ctypes.c_double, [vp]),
+        "smrt_set_launch": (ctypes.c_int, [vp, i32, i32, i32]),
+        "smrt_synchronize": (ctypes.c_int, [vp]),
+        "smrt_destroy": (None, [vp]),
+        "smrt_last_error": (ctypes.c_char_p, []),
+        "smrt_copy_kernel": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != OK:
+        msg = load().smrt_last_error().decode(errors="replace")
+        raise (UnstableError if rc == EUNSTABLE else SmrtError)(rc, msg)
+    return rc
+
+
+def make_params(nx, ny, scheme="smrt", boundary="cavity", storage="f32", tau=None, re=None,
+                u_lid=0.0, tau_s=1.0, stream=0):
+    p = Params()
+    p.nx, p.ny = int(nx), int(ny)
+    p.scheme, p.boundary, p.storage = SCHEMES[scheme], BOUNDARIES[boundary], STORAGE[storage]
+    p.tau = float(tau) if tau is not None else 0.0
+    p.re = float(re) if re is not None else 0.0
+    p.u_lid, p.tau_s = float(u_lid), float(tau_s)
+    p.stream = int(stream) or None
+    return p
+
+
+def workspace_bytes(**kw):
+    """Workspace bytes for the given parameters (0 if they are invalid)."""
+    return int(load().smrt_workspace_bytes(ctypes.byref(make_params(**kw))))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Solver:
+    """One lattice on one GPU.
+
+    Parameters mirror ``smrt_params``: ``scheme`` in {'srt', 'smrt', 'trt'},
+    ``boundary`` in {'cavity', 'periodic'}, ``storage`` in {'f64', 'f32',
+    'f16', 'bf16'}; give ``tau`` directly or ``re`` (then tau = 3 U N / Re + 1/2).
+    The workspace is a torch uint8 tensor on ``device``; work goes to the
+    current torch stream of that device at construction time.
+    """
+
+    def __init__(self, nx, ny, scheme="smrt", boundary="cavity", storage="f32", tau=None,
+                 re=None, u_lid=0.0, tau_s=1.0, device="cuda:0"):
+        lib = load()
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("the solver runs on a GPU device, got %s" % self.device)
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+        self.nx, self.ny = int(nx), int(ny)
+        self.scheme, self.boundary, self.storage = scheme, boundary, storage
+        self._params = make_params(nx, ny, scheme, boundary, storage, tau, re, u_lid, tau_s,
+                                   self.stream.cuda_stream)
+        nbytes = lib.smrt_workspace_bytes(ctypes.byref(self._params))
+        if nbytes == 0:
+            _check(lib.smrt_create(ctypes.byref(self._params), None, 0,
+                                   ctypes.byref(ctypes.c_void_p())))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        ctx = ctypes.c_void_p()
+        _check(lib.smrt_create(ctypes.byref(self._params), _ptr(self.workspace), nbytes,
+                               ctypes.byref(ctx)))
+        self._ctx = ctx
+
+    # -- lifetime -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_ctx", None):
+            load().smrt_synchronize(self._ctx)
+            load().smrt_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- state --------------------------------------------------------------
+    @property
+    def tau(self):
+        return float(load().smrt_tau(self._ctx))
+
+    @property
+    def steps_done(self):
+        return int(load().smrt_steps_done(self._ctx))
+
+    def _io(self, t, shape):
+        if t is None:
+            return None
+        if t.device != self.device or not t.is_contiguous() or tuple(t.shape) != shape:
+            raise ValueError("expected a contiguous %s tensor of shape %s on %s" %
+                             (t.dtype, shape, self.device))
+        if t.dtype not in _IO_DTYPES:
+            raise ValueError("fields must be float32 or float64")
+        return t
+
+    def init_fields(self, rho=None, ux=None, uy=None):
+        """f = f^eq(rho, u); tensors (ny, nx) float32/float64 on the device."""
+        given = [t for t in (rho, ux, uy) if t is not None]
+        dtype = given[0].dtype if given else torch.float32
+        if any(t.dtype != dtype for t in given):
+            raise ValueError("rho, ux, uy must share one dtype")
+        s = (self.ny, self.nx)
+        _check(load().smrt_init_fields(self._ctx, _ptr(self._io(rho, s)), _ptr(self._io(ux, s)),
+                                       _ptr(self._io(uy, s)), _IO_DTYPES[dtype]))
+
+    def set_populations(self, f):
+        """Post-collision populations f, tensor (9, ny, nx) float32/float64."""
+        f = self._io(f, (9, self.ny, self.nx))
+        _check(load().smrt_set_populations(self._ctx, _ptr(f), _IO_DTYPES[f.dtype]))
+
+    def populations(self, dtype=torch.float64):
+        out = torch.empty((9, self.ny, self.nx), dtype=dtype, device=self.device)
+        _check(load().smrt_get_populations(self._ctx, _ptr(out), _IO_DTYPES[dtype]))
+        return out
+
+    def step(self, n=1):
+        _check(load().smrt_step(self._ctx, int(n)))
+
+    def moments(self, dtype=torch.float64):
+        s = (self.ny, self.nx)
+        rho, ux, uy = (torch.empty(s, dtype=dtype, device=self.device) for _ in range(3))
+        _check(load().smrt_moments(self._ctx, _ptr(rho), _ptr(ux), _ptr(uy), _IO_DTYPES[dtype]))
+        return rho, ux, uy
+
+    def residual(self):
+        out = ctypes.c_double()
+        _check(load().smrt_residual(self._ctx, ctypes.byref(out)))
+        return out.value
+
+    def mass(self):
+        out = ctypes.c_double()
+        _check(load().smrt_mass(self._ctx, ctypes.byref(out)))
+        return out.value
+
+    def set_launch(self, bx, by, rows=1):
+        _check(load().smrt_set_launch(self._ctx, int(bx), int(by), int(rows)))
+
+    def synchronize(self):
+        _check(load().smrt_synchronize(self._ctx))
+
+
+def copy_kernel(src, dst, nbytes=None, stream=None):
+    """Launches the library's reference streaming copy (src -> dst, device tensors)."""
+    nbytes = src.numel() * src.element_size() if nbytes is None else int(nbytes)
+    s = (stream or torch.cuda.current_stream(src.device)).cuda_stream
+    _check(load().smrt_copy_kernel(_ptr(src), _ptr(dst), nbytes, ctypes.c_void_p(s or None)))

@@ -1,0 +1,279 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle.
+
+Tolerances: FP64 storage agrees with the oracle to round-off (max|du| <= 1e-11 U
+after thousands of steps, the GPU fusing multiply-adds where the oracle does
+not); FP32 storage meets max|du|/U <= 1e-5 (U the lid speed, or u0 for the
+periodic fields).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2409_01076_amd import inputs
+from gpu_util import (gpu_fields, gpu_populations, max_vel_err, oracle_from_fields,
+                      oracle_from_post_collision, oracle_lattice, oracle_sample_periodic,
+                      require_gpu, to_dev, torch)
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-11, "f32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def smrt():
+    return require_gpu()
+
+
+# --- the 64 x 64 cavity at Re = 100, 2000 steps, both schemes, FP64 and FP32 -------------
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("scheme", ["smrt", "srt"])
+def test_cavity_64_re100_2000_steps(smrt, scheme, storage):
+    n, u, steps = 64, 0.1, 2000
+    with smrt.Solver(n, n, scheme=scheme, boundary="cavity", storage=storage, re=100.0,
+                     u_lid=u) as s:
+        assert abs(s.tau - 0.692) < 1e-15
+        s.step(steps)
+        g = gpu_fields(s)
+        gf = gpu_populations(s)
+        mass = s.mass()
+    L = O.Lattice(n, n, scheme, re=100.0, u_lid=u)
+    f = L.run(L.init_equilibrium(), steps)
+    o = L.fields(f)
+    err = max_vel_err(g, o) / u
+    print("cavity64 %s %s max|du|/U = %.3e" % (scheme, storage, err))
+    assert err <= TOL[storage]
+    assert abs(mass / (n * n) - 1) < (1e-13 if storage == "f64" else 1e-9)
+    if storage == "f64":
+        assert np.max(np.abs(gf - L.collide(f))) < 1e-14
+
+
+# --- one step from far-from-equilibrium populations: collision + streaming + walls -------
+
+@pytest.mark.parametrize("boundary", ["periodic", "cavity"])
+@pytest.mark.parametrize("scheme,tau,tau_s", [("srt", 0.57, 1.0), ("smrt", 0.57, 1.0),
+                                              ("smrt", 1.3, 1.0), ("trt", 0.6, 0.83)])
+@pytest.mark.parametrize("nx,ny", [(3, 3), (37, 29), (300, 70), (64, 256)])
+def test_one_step_from_nonequilibrium_populations(smrt, boundary, scheme, tau, tau_s, nx, ny):
+    f0 = inputs.perturbed_populations(nx, ny, eps=0.05, seed=nx * 1000 + ny)
+    u = 0.08 if boundary == "cavity" else 0.0
+    L = oracle_lattice(nx, ny, scheme, boundary, tau, u, tau_s)
+    want = L.collide(oracle_from_post_collision(L, np.moveaxis(f0, 0, -1), 1))
+    for storage, tol in (("f64", 1e-15), ("f32", 2e-8)):
+        with smrt.Solver(nx, ny, scheme=scheme, boundary=boundary, storage=storage, tau=tau,
+                         u_lid=u, tau_s=tau_s) as s:
+            s.set_populations(to_dev(f0, torch.float64))
+            s.step(1)
+            got = gpu_populations(s)
+        err = np.max(np.abs(got - want))
+        print("one-step %s %s %s %dx%d: %.3e" % (boundary, scheme, storage, nx, ny, err))
+        assert err < tol
+
+
+# --- multi-step periodic fields with ragged tiles, every scheme -------------------------
+
+@pytest.mark.parametrize("scheme", ["srt", "smrt", "trt"])
+@pytest.mark.parametrize("tau", [0.51, 0.6, 1.0])
+def test_periodic_taylor_green_ragged(smrt, scheme, tau):
+    nx, ny, steps, u0 = 300, 157, 300, 0.05
+    rho, ux, uy = inputs.taylor_green(nx, ny, u0=u0, noise=1e-3, seed=11)
+    L = oracle_lattice(nx, ny, scheme, "periodic", tau, tau_s=0.8)
+    o = L.fields(oracle_from_fields(L, rho, ux, uy, steps))
+    for storage in ("f64", "f32"):
+        with smrt.Solver(nx, ny, scheme=scheme, boundary="periodic", storage=storage, tau=tau,
+                         tau_s=0.8) as s:
+            s.init_fields(to_dev(rho), to_dev(ux), to_dev(uy))
+            s.step(steps)
+            g = gpu_fields(s)
+        err = max_vel_err(g, o) / u0
+        print("tg %s tau=%g %s: %.3e" % (scheme, tau, storage, err))
+        assert err <= TOL[storage]
+
+
+# --- the 1024 x 1024 cavity at Re = 1000 (tau = 0.8072) -----------------------------------
+
+@pytest.mark.parametrize("scheme", ["smrt", "srt"])
+def test_cavity_1024_re1000(smrt, scheme):
+    n, u, steps = 1024, 0.1, 200
+    with smrt.Solver(n, n, scheme=scheme, boundary="cavity", storage="f32", re=1000.0,
+                     u_lid=u) as s:
+        assert abs(s.tau - 0.8072) < 1e-15
+        s.step(steps)
+        g = gpu_fields(s)
+    L = O.Lattice(n, n, scheme, re=1000.0, u_lid=u)
+    o = L.fields(L.run(L.init_equilibrium(), steps))
+    err = max_vel_err(g, o) / u
+    print("cavity1024 %s f32: %.3e" % (scheme, err))
+    assert err <= TOL["f32"]
+
+
+# --- 4096 x 4096 periodic Taylor-Green, in the benchmark's launch configuration ----------
+
+TG_N, TG_U0 = 4096, 0.05
+SAMPLES = [(0, 0), (4095, 17), (2048, 2048), (1000, 3333), (77, 4095), (3071, 1)]
+
+
+@pytest.fixture(scope="module")
+def tg4096():
+    return inputs.taylor_green(TG_N, TG_N, u0=TG_U0, noise=1e-3)
+
+
+@pytest.mark.parametrize("scheme", ["smrt", "srt"])
+@pytest.mark.parametrize("tau", [0.51, 0.6, 1.0])
+def test_taylor_green_4096_sampled(smrt, tg4096, scheme, tau):
+    rho, ux, uy = tg4096
+    with smrt.Solver(TG_N, TG_N, scheme=scheme, boundary="periodic", storage="f32", tau=tau) as s:
+        s.init_fields(to_dev(rho), to_dev(ux), to_dev(uy))
+        m0 = s.mass()
+        s.step(64)
+        g = gpu_fields(s)
+        s.step(1000 - 64)
+        r1000, ux1000, uy1000 = s.moments(torch.float64)
+        m1 = s.mass()
+    want = oracle_sample_periodic((scheme, tau, 1.0), rho, ux, uy, SAMPLES, 64, chunk=8)
+    got = np.array([(g[0][c], g[1][c], g[2][c]) for c in SAMPLES])
+    err = np.max(np.abs(got[:, 1:] - want[:, 1:])) / TG_U0
+    print("tg4096 %s tau=%g sampled @64: %.3e" % (scheme, tau, err))
+    assert err <= TOL["f32"]
+    # after 1000 steps: mass and momentum conserved, field finite
+    assert abs(m1 / m0 - 1) < 1e-9
+    jx = float((r1000 * ux1000).sum()) / TG_N ** 2
+    jy = float((r1000 * uy1000).sum()) / TG_N ** 2
+    assert abs(jx) < 1e-8 and abs(jy) < 1e-8
+    assert bool(torch.isfinite(ux1000).all())
+
+
+def test_taylor_green_4096_sampled_after_1000_steps(smrt, tg4096):
+    """The full config step count for the stiffest case, on one sampled node."""
+    rho, ux, uy = tg4096
+    scheme, tau = "smrt", 0.51
+    with smrt.Solver(TG_N, TG_N, scheme=scheme, boundary="periodic", storage="f32", tau=tau) as s:
+        s.init_fields(to_dev(rho), to_dev(ux), to_dev(uy))
+        s.step(1000)
+        g = gpu_fields(s)
+    cell = [(1500, 2600)]
+    want = oracle_sample_periodic((scheme, tau, 1.0), rho, ux, uy, cell, 1000, chunk=50)
+    err = max(abs(g[1][cell[0]] - want[0, 1]), abs(g[2][cell[0]] - want[0, 2])) / TG_U0
+    print("tg4096 smrt tau=0.51 sampled @1000: %.3e" % err)
+    assert err <= TOL["f32"]
+
+
+# --- residual and mass against the oracle's reductions ----------------------------------
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_residual_and_mass_match_oracle(smrt, storage):
+    n, u = 48, 0.1
+    L = O.Lattice(n, n, "smrt", re=200.0, u_lid=u)
+    f = L.run(L.init_equilibrium(), 300)
+    _, sx, sy = L.fields(f)
+    f2 = L.run(f, 200)
+    r2, ux2, uy2 = L.fields(f2)
+    want_r = O.residual(ux2, uy2, sx, sy, 200)
+    want_m = O.reduce(r2, ux2, uy2, sx, sy)[2]
+    with smrt.Solver(n, n, scheme="smrt", boundary="cavity", storage=storage, re=200.0,
+                     u_lid=u) as s:
+        s.step(300)
+        s.residual()               # snapshot at step 300
+        s.step(200)
+        got_r = s.residual()
+        got_m = s.mass()
+    rtol = 1e-9 if storage == "f64" else 1e-3
+    assert abs(got_r / want_r - 1) < rtol
+    assert abs(got_m - want_m) < (1e-10 if storage == "f64" else 1e-6)
+
+
+# --- determinism, edge cases, error paths -------------------------------------------------
+
+def test_bitwise_deterministic_across_runs_and_launch_shapes(smrt):
+    n = 200
+    rho, ux, uy = inputs.taylor_green(n, n + 3, u0=0.05, seed=3)
+    outs = []
+    for shape in ((64, 4, 1), (64, 4, 1), (128, 2, 3), (256, 1, 2), (16, 16, 1)):
+        with smrt.Solver(n, n + 3, scheme="smrt", boundary="periodic", storage="f32", tau=0.55) as s:
+            s.set_launch(*shape)
+            s.init_fields(to_dev(rho), to_dev(ux), to_dev(uy))
+            s.step(50)
+            outs.append(s.populations(torch.float32).cpu().numpy())
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_residual_requires_a_step_and_zero_steps_is_noop(smrt):
+    with smrt.Solver(16, 16, scheme="smrt", boundary="cavity", storage="f32", re=100.0,
+                     u_lid=0.1) as s:
+        with pytest.raises(smrt.SmrtError) as e:
+            s.residual()
+        assert e.value.code == smrt.ESTATE
+        before = s.populations(torch.float64)
+        s.step(0)
+        assert torch.equal(before, s.populations(torch.float64)) and s.steps_done == 0
+        with pytest.raises(smrt.SmrtError):
+            s.step(-1)
+        s.step(3)
+        assert s.residual() > 0 and s.steps_done == 3
+
+
+def test_cavity_at_rest_has_zero_residual(smrt):
+    with smrt.Solver(20, 20, scheme="smrt", boundary="cavity", storage="f32", tau=0.7,
+                     u_lid=0.0) as s:
+        s.step(10)
+        assert s.residual() == 0.0
+        assert abs(s.mass() - 400) < 1e-12
+
+
+def test_nan_injection_is_reported_unstable(smrt):
+    n = 24
+    rho = np.ones((n, n), np.float32)
+    rho[5, 7] = np.nan
+    with smrt.Solver(n, n, scheme="smrt", boundary="periodic", storage="f32", tau=0.6) as s:
+        s.init_fields(to_dev(rho), None, None)
+        s.step(2)
+        with pytest.raises(smrt.UnstableError):
+            s.residual()
+        with pytest.raises(smrt.UnstableError):
+            s.mass()
+
+
+def test_stability_contrast_on_gpu(smrt):
+    """SRT blows up at tau = 0.51 with a fast lid on 100^2 while SmrtLBM does not."""
+    with smrt.Solver(100, 100, scheme="srt", boundary="cavity", storage="f32", tau=0.51,
+                     u_lid=0.1667) as s:
+        s.step(1000)
+        with pytest.raises(smrt.UnstableError):
+            s.residual()
+    with smrt.Solver(100, 100, scheme="smrt", boundary="cavity", storage="f32", tau=0.51,
+                     u_lid=0.1667) as s:
+        s.step(20000)
+        r = s.residual()
+        assert np.isfinite(r)
+
+
+def test_mirror_symmetry_fp64(smrt):
+    outs = []
+    for u in (0.1, -0.1):
+        with smrt.Solver(40, 33, scheme="smrt", boundary="cavity", storage="f64", tau=0.6,
+                         u_lid=u) as s:
+            s.step(500)
+            outs.append(gpu_fields(s))
+    (_, ax, ay), (_, bx, by) = outs
+    assert np.max(np.abs(bx[:, ::-1] + ax)) < 1e-14 and np.max(np.abs(by[:, ::-1] - ay)) < 1e-14
+
+
+@pytest.mark.parametrize("nx,ny", [(3, 500), (700, 3), (3, 3)])
+def test_degenerate_shapes(smrt, nx, ny):
+    for boundary, u in (("cavity", 0.1), ("periodic", 0.0)):
+        L = O.Lattice(nx, ny, "smrt", tau=0.7, u_lid=u, boundary=boundary)
+        o = L.fields(L.run(L.init_equilibrium(), 50))
+        with smrt.Solver(nx, ny, scheme="smrt", boundary=boundary, storage="f64", tau=0.7,
+                         u_lid=u) as s:
+            s.step(50)
+            g = gpu_fields(s)
+        assert max_vel_err(g, o) < 1e-13
+
+
+def test_copy_kernel(smrt):
+    a = torch.arange(1 << 20, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    smrt.copy_kernel(a, b)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)

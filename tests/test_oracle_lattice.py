@@ -210,3 +210,20 @@ def test_reduce_sums_and_nonfinite_count():
     du2, u2, mass, bad = O.reduce(rho[:3], ux[:3], uy[:3], sx[:3], sy[:3])
     assert (du2, u2, mass, bad) == (2.0, 2.0, 6.0, 0.0)
     assert abs(O.residual(ux[:3], uy[:3], sx[:3], sy[:3], 4) - np.sqrt(2) / (4 * np.sqrt(2))) < 1e-16
+
+
+@pytest.mark.parametrize("scheme", ["srt", "smrt"])
+def test_window_sampling_equals_full_periodic_run(scheme):
+    """The shrinking-window sampler used by the large GPU parity tests reproduces
+    the full-lattice oracle exactly at the sampled nodes."""
+    from gpu_util import oracle_sample_periodic
+    from paper_2409_01076_amd import inputs
+    n, steps = 48, 20
+    rho, ux, uy = inputs.taylor_green(n, n, u0=0.05, seed=5)
+    L = O.Lattice(n, n, scheme, tau=0.55, boundary="periodic")
+    full = L.fields(L.run(L.init_equilibrium(rho.astype(float), ux.astype(float),
+                                             uy.astype(float)), steps))
+    cells = [(0, 0), (47, 3), (20, 30)]
+    got = oracle_sample_periodic((scheme, 0.55, 1.0), rho, ux, uy, cells, steps, chunk=6)
+    for i, c in enumerate(cells):
+        assert np.array_equal(got[i], [full[0][c], full[1][c], full[2][c]])
