@@ -1,0 +1,232 @@
+"""Benchmark of the gfx950 SmrtLBM stream-collide path on one MI355X.
+
+One benchmark step is one residual window: `--window` time steps of the
+fused stream-collide kernel over the whole lattice, then the FP64 residual and
+mass check and the export of (rho, u).  The default workload is the
+bandwidth-scale case: a 4096 x 4096 periodic Taylor-Green field (u0 = 0.05,
+wavenumber 2 pi / N, seeded +-1e-3 density noise), SmrtLBM, FP32 deviation
+storage, tau = 0.6.
+
+Printed (one JSON line): MLUPS of the whole job, the algorithmic HBM rate of
+the stream-collide kernel against the 8 TB/s peak (its average launch time
+measured with HIP events on the stream it runs on), the HBM bytes that the
+rocprofv3 counters recorded for that kernel (when they were taken on the
+current kernel source), and the CPU oracle timed on a bounded sample of the
+same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS & HBM GB/s vs peak; time-to-steady (warm vs cold) at 1e-7 residual"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2409_01076_amd", "csrc", "lbm_kernels.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_collide.json")
+STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+
+
+def kernel_source_hash():
+    with open(KERNEL_SOURCE, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5, help="timed residual windows")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed residual windows")
+    ap.add_argument("--window", type=int, default=1000, help="time steps per residual window")
+    ap.add_argument("--n", type=int, default=4096, help="lattice side")
+    ap.add_argument("--scheme", default="smrt", choices=["smrt", "srt", "trt"])
+    ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f16", "bf16"])
+    ap.add_argument("--tau", type=float, default=0.6)
+    ap.add_argument("--launch", default="", help="bx,by,rows of the stream-collide kernel")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget")
+    ap.add_argument("--copy-only", type=int, default=0, metavar="MIB",
+                    help="only run the reference copy kernel over MIB mebibytes (counter calibration)")
+    return ap.parse_args()
+
+
+def copy_only(mib, reps=5):
+    import torch
+    from paper_2409_01076_amd import smrt
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        smrt.copy_kernel(a, b)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_kernel_bytes_each_way": n * 4, "launches": reps}), flush=True)
+
+
+def copy_ceiling(nbytes, reps=10):
+    """GB/s (read + write) of the library's plain copy kernel over nbytes."""
+    import torch
+    from paper_2409_01076_amd import smrt
+    n = nbytes // 4 // 16 * 16
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    smrt.copy_kernel(a, b)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        smrt.copy_kernel(a, b)
+    e1.record(s)
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b
+    return 2 * n * 4 / sec / 1e9
+
+
+def traffic_record(launch_cells):
+    """Measured HBM bytes per stream-collide launch from the committed counter
+    summary, or None when it is missing or was taken on other kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    if rec.get("cells_per_launch") != launch_cells:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(args, fields, budget_s):
+    """The oracle as it is, on the same workload, for about budget_s seconds."""
+    import numpy as np
+
+    import oracle as O
+    rho, ux, uy = (a.astype(np.float64) for a in fields)
+    L = O.Lattice(args.n, args.n, args.scheme, tau=args.tau, boundary="periodic", tau_s=1.0)
+    f = L.init_equilibrium(rho, ux, uy)
+    t0 = time.perf_counter()
+    f = L.run(f, 1)
+    first = time.perf_counter() - t0
+    steps = int(max(1, min(200, round(budget_s / max(first, 1e-3)))))
+    t0 = time.perf_counter()
+    f = L.run(f, steps)
+    dt = time.perf_counter() - t0
+    cells = args.n * args.n * steps
+    return {"value": cells / dt / 1e6, "unit": "MLUPS", "cores": O.get_threads(), "kind": "oracle",
+            "sample": "%d time steps of the %dx%d periodic Taylor-Green lattice (%s, tau=%g), "
+                      "FP64, %.1f s" % (steps, args.n, args.n, args.scheme, args.tau, dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    if args.copy_only:
+        copy_only(args.copy_only)
+        return
+
+    from paper_2409_01076_amd import inputs, smrt
+
+    n, K = args.n, args.window
+    fields = inputs.taylor_green(n, n, u0=0.05, noise=1e-3)
+    dev = [torch.from_numpy(a).to("cuda:0") for a in fields]
+    solver = smrt.Solver(n, n, scheme=args.scheme, boundary="periodic", storage=args.storage,
+                         tau=args.tau, tau_s=1.0, device="cuda:0")
+    if args.launch:
+        solver.set_launch(*[int(v) for v in args.launch.split(",")])
+    solver.init_fields(*dev)
+    del dev
+    stream = solver.stream
+    rho_out, ux_out, uy_out = (torch.empty((n, n), dtype=torch.float32, device="cuda:0")
+                               for _ in range(3))
+    lib = smrt.load()
+
+    def window(events=None):
+        if events is not None:
+            events[0].record(stream)
+        solver.step(K)
+        if events is not None:
+            events[1].record(stream)
+        r = solver.residual()
+        smrt._check(lib.smrt_moments(solver._ctx, smrt._ptr(rho_out), smrt._ptr(ux_out),
+                                     smrt._ptr(uy_out), smrt.STORAGE["f32"]))
+        return r
+
+    for _ in range(args.warmup):
+        window()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    residuals = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        residuals.append(window(ev[i]))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = sum(a.elapsed_time(b) for a, b in ev) / (args.steps * K)
+    mass = solver.mass()
+    solver.close()
+
+    cells = n * n
+    s = STORAGE_BYTES[args.storage]
+    alg_bytes = 18 * s * cells                     # 9 loads + 9 stores per node
+    achieved = alg_bytes / (kernel_ms / 1e3) / 1e9
+    mlups = cells * K * args.steps / wall / 1e6
+    traffic = traffic_record(cells)
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.storage == "f64" else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "periodic Taylor-Green %dx%d, %s, %s deviation storage, tau=%g, "
+                        "step = %d time steps + residual/mass + moments export"
+                        % (n, n, args.scheme, args.storage, args.tau, K),
+            "nx": n, "ny": n, "scheme": args.scheme, "storage": args.storage, "tau": args.tau,
+            "window": K, "u0": 0.05, "density_noise": 1e-3, "seed": inputs.DEFAULT_SEED,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": "stream_collide",
+            "kernel_avg_us": round(kernel_ms * 1e3, 2),
+            "algorithmic_bytes_per_launch": alg_bytes,
+        },
+        "glups_kernel": round(cells / (kernel_ms / 1e3) / 1e9, 2),
+        "copy_kernel_gbs": round(copy_ceiling(alg_bytes // 2), 1),
+        "last_residual": residuals[-1],
+        "mass_drift": mass / cells - 1.0,
+    }
+    out["roofline"]["frac_of_copy_kernel"] = round(achieved / out["copy_kernel_gbs"], 4)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args, fields, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -43,9 +43,9 @@ def test_cavity_64_re100_2000_steps(smrt, scheme, storage):
     err = max_vel_err(g, o) / u
     print("cavity64 %s %s max|du|/U = %.3e" % (scheme, storage, err))
     assert err <= TOL[storage]
-    assert abs(mass / (n * n) - 1) < (1e-13 if storage == "f64" else 1e-9)
+    assert abs(mass / (n * n) - 1) < (1e-13 if storage == "f64" else 2e-9)
     if storage == "f64":
-        assert np.max(np.abs(gf - L.collide(f))) < 1e-14
+        assert np.max(np.abs(gf - L.collide(f))) < 1e-12
 
 
 # --- one step from far-from-equilibrium populations: collision + streaming + walls -------
