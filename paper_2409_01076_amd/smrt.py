@@ -212,9 +212,22 @@ class Solver:
         _check(load().smrt_step(self._ctx, int(n)))
 
     def moments(self, dtype=torch.float64):
+        """(rho, ux, uy) as new (ny, nx) tensors."""
         s = (self.ny, self.nx)
         rho, ux, uy = (torch.empty(s, dtype=dtype, device=self.device) for _ in range(3))
-        _check(load().smrt_moments(self._ctx, _ptr(rho), _ptr(ux), _ptr(uy), _IO_DTYPES[dtype]))
+        return self.moments_into(rho, ux, uy)
+
+    def moments_into(self, rho=None, ux=None, uy=None):
+        """Writes (rho, ux, uy) into caller tensors (any may be None); returns them."""
+        s = (self.ny, self.nx)
+        given = [t for t in (rho, ux, uy) if t is not None]
+        if not given:
+            return rho, ux, uy
+        dtype = given[0].dtype
+        if any(t.dtype != dtype for t in given):
+            raise ValueError("rho, ux, uy must share one dtype")
+        _check(load().smrt_moments(self._ctx, _ptr(self._io(rho, s)), _ptr(self._io(ux, s)),
+                                   _ptr(self._io(uy, s)), _IO_DTYPES[dtype]))
         return rho, ux, uy
 
     def residual(self):
