@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -56,6 +58,20 @@ def parse():
     ap.add_argument("--launch", default="", help="bx,by,rows of the stream-collide kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget")
+    ap.add_argument("--workload", default="tg", choices=["tg", "cavity", "precision", "batch"],
+                    help="tg: periodic Taylor-Green throughput (default); cavity: lid-driven "
+                         "cavity run from the cold start to the steady-state residual; "
+                         "precision: one cavity in every storage type against FP64; "
+                         "batch: many cavities of uneven size and Re run together to steady")
+    ap.add_argument("--count", type=int, default=256, help="batch: number of cavities")
+    ap.add_argument("--schedule", default="",
+                    help="cavity: precision schedule 'f16:1e-5' = run in that storage until the "
+                         "residual falls below the level, then convert to --storage and finish")
+    ap.add_argument("--compare-steps", type=int, default=200_000,
+                    help="precision: step count at which the storage types are compared")
+    ap.add_argument("--re", type=float, default=1000.0, help="cavity Reynolds number")
+    ap.add_argument("--tol", type=float, default=1e-7, help="cavity steady-state residual")
+    ap.add_argument("--max-steps", type=int, default=3_000_000, help="cavity step cap")
     ap.add_argument("--copy-only", type=int, default=0, metavar="MIB",
                     help="only run the reference copy kernel over MIB mebibytes (counter calibration)")
     return ap.parse_args()
@@ -130,6 +146,183 @@ def cpu_baseline(args, fields, budget_s):
                       "FP64, %.1f s" % (steps, args.n, args.n, args.scheme, args.tau, dt)}
 
 
+def cavity_to_steady(args):
+    """Cold-start lid-driven cavity (U = 0.1) run until the windowed residual
+    falls below args.tol: steps, wall time and throughput for each scheme."""
+    import torch
+    from paper_2409_01076_amd import smrt
+    n = args.n if args.n != 4096 else 1024
+    results = {}
+    stages = []
+    if args.schedule:
+        first, level = args.schedule.split(":")
+        stages.append((first, float(level)))
+    stages.append((args.storage, args.tol))
+    for scheme in ("smrt", "srt"):
+        solver = smrt.Solver(n, n, scheme=scheme, boundary="cavity", storage=stages[0][0],
+                             re=args.re, u_lid=0.1, device="cuda:0")
+        if args.launch:
+            solver.set_launch(*[int(v) for v in args.launch.split(",")])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        last = [0.0]
+
+        def progress(steps, r):
+            if time.perf_counter() - last[0] > 20:
+                last[0] = time.perf_counter()
+                print("# %s step %d residual %.3e" % (scheme, steps, r), file=sys.stderr, flush=True)
+        steps, res, status, stage_steps = 0, [], "cap", []
+        try:
+            for i, (storage, level) in enumerate(stages):
+                if i > 0:
+                    old = solver
+                    solver = old.convert(storage)
+                    old.close()
+                k, r, ok = solver.run_to_steady(level, args.window, args.max_steps - steps, progress)
+                steps += k
+                res += r
+                stage_steps.append(k)
+                if not ok:
+                    break
+            else:
+                status = "steady"
+        except smrt.UnstableError:
+            steps, status = steps + solver.steps_done, "unstable"
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        results[scheme] = {"steps": steps, "seconds": round(wall, 3), "status": status,
+                           "final_residual": res[-1] if res else None,
+                           "mlups": round(n * n * steps / wall / 1e6, 1), "tau": solver.tau,
+                           "stages": [{"storage": st, "until": lv, "steps": k}
+                                      for (st, lv), k in zip(stages, stage_steps)]}
+        solver.close()
+    s = results["smrt"]
+    out = {
+        "metric": METRIC, "value": s["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": s["steps"],
+        "warmup": 0, "ms_per_step": round(s["seconds"] / max(1, s["steps"]) * 1e3, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.storage == "f64" else "f32", "data": "synthetic",
+        "config": {"workload": "lid-driven cavity %dx%d, Re=%g, U=0.1, %s storage%s, cold start, "
+                               "run to windowed residual < %g (window %d)"
+                               % (n, n, args.re, args.storage,
+                                  " after " + args.schedule if args.schedule else "", args.tol,
+                                  args.window),
+                   "schedule": args.schedule or None,
+                   "nx": n, "ny": n, "re": args.re, "u_lid": 0.1, "storage": args.storage,
+                   "window": args.window, "tol": args.tol},
+        "time_to_steady": results,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def precision_study(args):
+    """The cold-start cavity (U = 0.1) in FP64, FP32, FP16 and BF16 storage.
+    Each is compared with the FP64 run (itself within round-off of the CPU
+    oracle) after --compare-steps steps: max |du| / U.  Then each runs on to
+    the steady-state residual (or the cap): steps, seconds and the error of
+    its final field against the FP64 final field."""
+    import torch
+    from paper_2409_01076_amd import smrt
+    n = args.n if args.n != 4096 else 2048
+    U = 0.1
+    ref, out = None, {}
+    for storage in ("f64", "f32", "f16", "bf16"):
+        s = smrt.Solver(n, n, scheme=args.scheme, boundary="cavity", storage=storage, re=args.re,
+                        u_lid=U, device="cuda:0")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(args.compare_steps)
+        _, ux, uy = s.moments(torch.float64)
+        torch.cuda.synchronize()
+        t_cmp = time.perf_counter() - t0
+        rec = {"seconds_to_compare": round(t_cmp, 3),
+               "mlups": round(n * n * args.compare_steps / t_cmp / 1e6, 1)}
+        if ref is None:
+            ref = (ux, uy)
+        else:
+            rec["max_du_over_U_at_compare"] = float(max((ux - ref[0]).abs().max(),
+                                                         (uy - ref[1]).abs().max())) / U
+        m0 = float(n * n)
+        rec["mass_drift_at_compare"] = s.mass() / m0 - 1.0
+        del ux, uy
+        last = [time.perf_counter()]
+
+        def progress(k, r, storage=storage):
+            if time.perf_counter() - last[0] > 20:
+                last[0] = time.perf_counter()
+                print("# %s step %d residual %.3e" % (storage, k, r), file=sys.stderr, flush=True)
+        try:
+            steps, res, ok = s.run_to_steady(args.tol, args.window, args.max_steps, progress)
+            status = "steady" if ok else "cap"
+            final = res[-1]
+        except smrt.UnstableError:
+            steps, status, final = s.steps_done, "unstable", None
+        torch.cuda.synchronize()
+        rec.update({"status": status, "steps_total": args.compare_steps + steps,
+                    "seconds_total": round(time.perf_counter() - t0, 3), "final_residual": final})
+        _, fx, fy = s.moments(torch.float64)
+        if storage == "f64":
+            ref_final = (fx, fy)
+        else:
+            rec["max_du_over_U_final"] = float(max((fx - ref_final[0]).abs().max(),
+                                                   (fy - ref_final[1]).abs().max())) / U
+        rec["mass_drift_final"] = s.mass() / m0 - 1.0
+        s.close()
+        out[storage] = rec
+        print("# %s %s" % (storage, json.dumps(rec)), file=sys.stderr, flush=True)
+    print(json.dumps({"workload": "precision: cavity %dx%d Re=%g U=%g %s, compared at %d steps "
+                                  "and at the residual %g (window %d, cap %d)"
+                                  % (n, n, args.re, U, args.scheme, args.compare_steps, args.tol,
+                                     args.window, args.max_steps),
+                      "reference": "FP64 storage on the GPU (round-off parity with the FP64 CPU oracle)",
+                      "results": out}), flush=True)
+
+
+def batch_to_steady(args):
+    """args.count cavities, side N = round(64 * 8^u) and Re = 100 * 100^v with
+    u, v ~ U(0, 1) from the seed, U = 0.1, all advanced together (one launch
+    per step, graph-captured windows, autotuned launch shape) until each is
+    steady (windowed residual < args.tol), unstable, or at args.max_steps."""
+    import torch
+    from paper_2409_01076_amd import inputs, smrt
+    n, re = inputs.cavity_batch(args.count, 64, 512, 100.0, 10000.0)
+    nodes = n.astype(np.int64) ** 2
+    b = smrt.Batch(n, n, scheme=args.scheme, storage=args.storage, re=re, u_lid=0.1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    chosen = b.autotune(steps=20)
+    tune_steps = b.steps_done
+    steps, status, res = b.run(args.tol, args.window, args.max_steps - tune_steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    b.close()
+    steps = np.array(steps)
+    updates = int((nodes * steps).sum())
+    st = np.array(status)
+    out = {
+        "metric": METRIC, "value": round(updates / wall / 1e6, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": int(steps.max()), "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.storage == "f64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": "%d lid-driven cavities, N log-uniform [64, 512], Re log-uniform "
+                               "[100, 1e4], U=0.1, %s, %s storage, each to residual < %g or %d steps"
+                               % (args.count, args.scheme, args.storage, args.tol, args.max_steps),
+                   "count": args.count, "seed": inputs.DEFAULT_SEED, "window": args.window,
+                   "total_nodes": int(nodes.sum())},
+        "cavities_per_second": round(args.count / wall, 3),
+        "seconds": round(wall, 3),
+        "node_updates": updates,
+        "autotuned_launch": {"bx": chosen[0], "by": chosen[1], "grid": chosen[2]},
+        "steady": int((st == smrt.STEADY).sum()), "unstable": int((st == smrt.UNSTABLE).sum()),
+        "capped": int((st == smrt.RUNNING).sum()),
+        "per_cavity": [{"n": int(a), "re": round(float(r), 2), "steps": int(k),
+                        "status": ["cap", "steady", "unstable"][int(s)],
+                        "residual": None if not np.isfinite(x) else float(x)}
+                       for a, r, k, s, x in zip(n, re, steps, status, res)],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -143,6 +336,16 @@ def main():
         sys.exit(1)
     if args.copy_only:
         copy_only(args.copy_only)
+        return
+
+    if args.workload == "cavity":
+        cavity_to_steady(args)
+        return
+    if args.workload == "precision":
+        precision_study(args)
+        return
+    if args.workload == "batch":
+        batch_to_steady(args)
         return
 
     from paper_2409_01076_amd import inputs, smrt

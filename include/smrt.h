@@ -168,6 +168,89 @@ void smrt_destroy(smrt_ctx* c);
 /* Message describing the last error on the calling thread ("" if none). */
 const char* smrt_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent lid-driven cavities (each a square or
+ * rectangular cavity of the paper's test section, with its own size and
+ * relaxation time) advanced together.  One time step of the whole batch is
+ * one kernel launch: a fixed grid of workgroups walks a device table of the
+ * tiles of the cavities still running.  Steps run in windows replayed from a
+ * captured HIP graph; after each window every running cavity's residual is
+ * checked and the cavities that reached the tolerance, or hold a non-finite
+ * value, leave the table.  Per node, the arithmetic is that of smrt_step, so
+ * a cavity's result does not depend on the batch it runs in.
+ * ------------------------------------------------------------------------ */
+
+typedef struct smrt_batch_params {
+    int32_t count;        /* number of cavities, >= 1                          */
+    int32_t scheme;       /* smrt_scheme                                       */
+    int32_t storage;      /* smrt_dtype of the stored populations              */
+    int32_t reserved0;    /* must be 0                                         */
+    const int32_t* nx;    /* host array [count], each >= 3                     */
+    const int32_t* ny;    /* host array [count], each >= 3                     */
+    const double* tau;    /* host array [count]; NULL or entries <= 0: derived
+                             from re as for smrt_params                        */
+    const double* re;     /* host array [count] or NULL                        */
+    double u_lid;         /* lid speed shared by all cavities                  */
+    double tau_s;         /* TRT only                                          */
+    void* stream;         /* hipStream_t, NULL for the default stream          */
+    int64_t reserved[4];  /* must be 0                                         */
+} smrt_batch_params;
+
+typedef struct smrt_batch smrt_batch;
+
+typedef enum smrt_batch_status {
+    SMRT_RUNNING = 0,  /* still in the table                                   */
+    SMRT_STEADY = 1,   /* residual fell below the tolerance                    */
+    SMRT_UNSTABLE = 2  /* a density or velocity became non-finite              */
+} smrt_batch_status;
+
+/* Device workspace bytes for a batch (0 if the parameters are invalid). */
+size_t smrt_batch_workspace_bytes(const smrt_batch_params* p);
+
+/* Creates a batch, every cavity at the cold start (rho = 1, u = 0), all
+ * running.  dev_ws as for smrt_create (caller-owned or NULL).  The library
+ * also allocates small device tables, a pinned host buffer and one private
+ * capture stream (default priority).  Errors as for smrt_create. */
+int smrt_batch_create(const smrt_batch_params* p, void* dev_ws, size_t ws_bytes, smrt_batch** out);
+
+/* Enqueues n time steps of every running cavity (asynchronous). */
+int smrt_batch_step(smrt_batch* b, int64_t n);
+
+/* Runs windows of `window` steps until every cavity is steady, unstable or
+ * has run max_steps steps in this call.  After each window the per-cavity
+ * residual (definition of smrt_residual, over that window) is compared with
+ * tol and finished cavities leave the table.  steps_out (host [count], may be
+ * NULL) receives each cavity's total steps when it finished (or so far);
+ * status_out (host [count], may be NULL) its smrt_batch_status; residual_out
+ * (host [count], may be NULL) its last residual.  Synchronizes. */
+int smrt_batch_run(smrt_batch* b, double tol, int64_t window, int64_t max_steps, int64_t* steps_out,
+                   int32_t* status_out, double* residual_out);
+
+/* Chooses the tile shape (bx, by) and the number of resident workgroups of
+ * the batch kernel by timing `steps` real steps (an even number >= 2) of each
+ * candidate; keeps the fastest.  chosen (host [3], may be NULL) receives
+ * bx, by and the grid size.  The trial steps advance every running cavity. */
+int smrt_batch_autotune(smrt_batch* b, int32_t steps, int32_t* chosen);
+
+/* Fields of cavity `index` (dense device arrays [ny][nx], F32 or F64; any may
+ * be NULL), from its current state. */
+int smrt_batch_moments(smrt_batch* b, int32_t index, void* rho, void* ux, void* uy, int32_t dtype);
+
+/* f = f^eq(rho, u) for cavity `index` (device fields as smrt_init_fields,
+ * NULL = rest); resets its snapshot.  Only while the cavity is running and
+ * before smrt_batch_run. */
+int smrt_batch_init_fields(smrt_batch* b, int32_t index, const void* rho, const void* ux,
+                           const void* uy, int32_t dtype);
+
+/* Steps taken by the running cavities since creation. */
+int64_t smrt_batch_steps_done(const smrt_batch* b);
+
+/* Number of cavities still running. */
+int32_t smrt_batch_running(const smrt_batch* b);
+
+/* Frees what the library allocated (not the caller's workspace). NULL: no-op. */
+void smrt_batch_destroy(smrt_batch* b);
+
 /* Bandwidth reference: copies `bytes` (a multiple of 16) from src to dst,
  * both device pointers 16-byte aligned, with a plain streaming copy kernel on
  * `stream`.  Used to calibrate byte counters and as the attainable read+write

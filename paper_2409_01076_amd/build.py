@@ -1,7 +1,8 @@
 """Compile the gfx950 HIP library ``libsmrt.so`` in-tree.
 
-One translation unit (``csrc/smrt_api.hip``, which includes the kernels) is
-compiled by hipcc for gfx950 only.  Packed-FP32 instructions are disabled on
+Two translation units (``csrc/smrt_api.hip``: single lattices; ``csrc/smrt_batch.hip``:
+cavity batches; both include the kernel headers) are compiled by hipcc for
+gfx950 only and linked into one shared library.  Packed-FP32 instructions are disabled on
 purpose (``-packed-fp32-ops``): the kernels are bandwidth-bound and gain
 nothing from them.
 """
@@ -11,7 +12,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "smrt_api.hip")
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("smrt_api.hip", "smrt_batch.hip")]
 LIB = os.path.join(HERE, "libsmrt.so")
 ARCH = "gfx950"
 
@@ -28,7 +29,7 @@ FLAGS = [
 def build(verbose: bool = False, extra=()) -> str:
     """Compile the library; returns its path.  Always recompiles."""
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, *FLAGS, *extra, SRC, "-o", tmp]
+    cmd = [HIPCC, *FLAGS, *extra, *SRCS, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -1,0 +1,161 @@
+// batch_kernels.hpp -- gfx950 device code for many independent lid-driven
+// cavities advanced together, one launch per time step for the whole batch.
+//
+// Every cavity keeps its own two structure-of-arrays population buffers and
+// its own velocity snapshot inside one workspace.  A device table lists the
+// tiles (bx x by nodes) of the cavities still running; a fixed grid of
+// workgroups walks that table (grid-stride), so one launch covers any mix of
+// sizes and the table can shrink as cavities finish without changing the
+// launch or a captured graph.  The per-node update is the same gather /
+// collide / store as the single-lattice kernel, so a cavity in a batch is
+// bitwise identical to the same cavity run alone.
+#pragma once
+
+#include "lbm_kernels.hpp"
+
+namespace smrt {
+
+struct CavityDesc {
+    int nx, ny, pitch, tiles_x;
+    int64_t plane;   // elements per direction plane
+    int64_t off[2];  // element offsets of buffer 0 and buffer 1
+    int64_t snap;    // offset (doubles) of the ux snapshot; uy follows after nx*ny
+    double omega, omega_s, a, b, lid;
+};
+
+struct BatchLaunch {
+    int bx, by;
+};
+
+template <typename C> __device__ __forceinline__ Coef<C> coef_of(const CavityDesc& c)
+{
+    Coef<C> k;
+    k.omega = (C)c.omega;
+    k.omega_s = (C)c.omega_s;
+    k.a = (C)c.a;
+    k.b = (C)c.b;
+    k.lid = (C)c.lid;
+    return k;
+}
+
+// One time step of every listed tile.  `parity` selects the source buffer.
+template <typename T, int SCHEME>
+__global__ void __launch_bounds__(1024) batch_stream_collide(const CavityDesc* __restrict__ cav,
+                                                             const int2* __restrict__ tiles,
+                                                             const int* __restrict__ ntiles_p,
+                                                             T* __restrict__ base, int parity,
+                                                             BatchLaunch L)
+{
+    using C = typename Storage<T>::C;
+    const int ntiles = *ntiles_p;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int2 tt = tiles[t];
+        const CavityDesc c = cav[tt.x];
+        Geom g;
+        g.nx = c.nx;
+        g.ny = c.ny;
+        g.pitch = c.pitch;
+        g.plane = c.plane;
+        g.bx = L.bx;
+        g.by = L.by;
+        g.rows = 1;
+        g.tiles_x = c.tiles_x;
+        const int x = (tt.y % c.tiles_x) * L.bx + threadIdx.x;
+        const int y = (tt.y / c.tiles_x) * L.by + threadIdx.y;
+        if (x >= c.nx || y >= c.ny) continue;
+        const T* src = base + c.off[parity];
+        T* dst = base + c.off[parity ^ 1];
+        C d[9];
+        const bool edge = (x == 0) | (x == c.nx - 1) | (y == 0) | (y == c.ny - 1);
+        if (edge)
+            gather_edge<T, CAVITY>(src, g, x, y, d, (C)c.lid);
+        else
+            gather_interior<T>(src, g, x, y, d);
+        const Coef<C> k = coef_of<C>(c);
+        collide<SCHEME, T>(d, k);
+        scatter_store<T>(dst, g, x, y, d);
+    }
+}
+
+// Per-tile FP64 partial sums (|u - u_snap|^2, |u|^2, rho - 1, non-finite
+// nodes) of every listed tile, in a fixed order; optionally refreshes the
+// snapshots.  Block size must equal bx * by (<= RED_THREADS * 4).
+template <typename T>
+__global__ void __launch_bounds__(1024) batch_reduce_partials(const CavityDesc* __restrict__ cav,
+                                                              const int2* __restrict__ tiles,
+                                                              const int* __restrict__ ntiles_p,
+                                                              const T* __restrict__ base, int parity,
+                                                              BatchLaunch L, double* __restrict__ snap_base,
+                                                              int update, double* __restrict__ partials)
+{
+    __shared__ double lds[RED_VALUES][16];
+    const int ntiles = *ntiles_p;
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    const int nwaves = (blockDim.x * blockDim.y + 63) / 64;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int2 tt = tiles[t];
+        const CavityDesc c = cav[tt.x];
+        const int x = (tt.y % c.tiles_x) * L.bx + threadIdx.x;
+        const int y = (tt.y / c.tiles_x) * L.by + threadIdx.y;
+        double s[RED_VALUES] = {0.0, 0.0, 0.0, 0.0};
+        if (x < c.nx && y < c.ny) {
+            Geom g;
+            g.plane = c.plane;
+            double drho, jx, jy;
+            node_moments_f64(base + c.off[parity], g, (int64_t)y * c.pitch + x, drho, jx, jy);
+            const double r = 1.0 + drho, vx = jx / r, vy = jy / r;
+            double* sx = snap_base + c.snap + (int64_t)y * c.nx + x;
+            double* sy = sx + (int64_t)c.nx * c.ny;
+            const double dx = vx - *sx, dy = vy - *sy;
+            s[0] = dx * dx + dy * dy;
+            s[1] = vx * vx + vy * vy;
+            s[2] = drho;
+            s[3] = (__builtin_isfinite(r) && __builtin_isfinite(vx) && __builtin_isfinite(vy)) ? 0.0 : 1.0;
+            if (update) {
+                *sx = vx;
+                *sy = vy;
+            }
+        }
+        const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+        for (int v = 0; v < RED_VALUES; ++v) {
+            const double w = wave_sum(s[v]);
+            if (lane == 0) lds[v][wave] = w;
+        }
+        __syncthreads();
+        if (tid < RED_VALUES) {
+            double acc = 0.0;
+            for (int w = 0; w < nwaves; ++w) acc += lds[tid][w];
+            partials[(int64_t)t * RED_VALUES + tid] = acc;
+        }
+        __syncthreads();
+    }
+}
+
+// One block per listed cavity: sums its tiles' partials (a contiguous range
+// of the table, in order) into out[cavity slot].
+__global__ void __launch_bounds__(RED_THREADS) batch_reduce_finish(const double* __restrict__ partials,
+                                                                   const int2* __restrict__ ranges,
+                                                                   double* __restrict__ out)
+{
+    __shared__ double lds[RED_VALUES][RED_WAVES];
+    const int2 r = ranges[blockIdx.x]; // (first tile, tile count)
+    double s[RED_VALUES] = {0.0, 0.0, 0.0, 0.0};
+    for (int p = threadIdx.x; p < r.y; p += RED_THREADS)
+#pragma unroll
+        for (int v = 0; v < RED_VALUES; ++v) s[v] += partials[(int64_t)(r.x + p) * RED_VALUES + v];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int v = 0; v < RED_VALUES; ++v) {
+        const double w = wave_sum(s[v]);
+        if (lane == 0) lds[v][wave] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < RED_VALUES) {
+        double acc = 0.0;
+        for (int w = 0; w < RED_WAVES; ++w) acc += lds[threadIdx.x][w];
+        out[(int64_t)blockIdx.x * RED_VALUES + threadIdx.x] = acc;
+    }
+}
+
+} // namespace smrt

@@ -26,35 +26,66 @@ struct bf16 {
     uint16_t bits;
 };
 
-// Storage traits: how a stored population converts to and from the
-// arithmetic type.  FP64 storage computes in FP64, everything else in FP32.
+// Storage traits: how a stored population d_a converts to and from the
+// arithmetic type C.  FP64 storage computes in FP64, everything else in FP32.
+//   load / store        the hot path (stores are non-temporal: written once,
+//                       read by the next step from HBM);
+//   stored_value(v, a)  v exactly as a store followed by a load returns it;
+//   to_f64 / from_f64   initialisation, export and reductions.
+// kRounds is true when stored_value is not the identity (16-bit storage).
 template <typename T> struct Storage;
 
 template <> struct Storage<double> {
     using C = double;
-    static __device__ __forceinline__ C load(const double* p) { return *p; }
-    static __device__ __forceinline__ void store(double* p, C v) { __builtin_nontemporal_store(v, p); }
-    static __device__ __forceinline__ double to_f64(const double* p) { return *p; }
-    static __device__ __forceinline__ void from_f64(double* p, double v) { *p = v; }
+    static constexpr bool kRounds = false;
+    static __device__ __forceinline__ C load(const double* p, int) { return *p; }
+    static __device__ __forceinline__ void store(double* p, int, C v) { __builtin_nontemporal_store(v, p); }
+    static __device__ __forceinline__ C stored_value(C v, int) { return v; }
+    static __device__ __forceinline__ double to_f64(const double* p, int) { return *p; }
+    static __device__ __forceinline__ void from_f64(double* p, int, double v) { *p = v; }
 };
 
 template <> struct Storage<float> {
     using C = float;
-    static __device__ __forceinline__ C load(const float* p) { return *p; }
-    static __device__ __forceinline__ void store(float* p, C v) { __builtin_nontemporal_store(v, p); }
-    static __device__ __forceinline__ double to_f64(const float* p) { return (double)*p; }
-    static __device__ __forceinline__ void from_f64(float* p, double v) { *p = (float)v; }
+    static constexpr bool kRounds = false;
+    static __device__ __forceinline__ C load(const float* p, int) { return *p; }
+    static __device__ __forceinline__ void store(float* p, int, C v) { __builtin_nontemporal_store(v, p); }
+    static __device__ __forceinline__ C stored_value(C v, int) { return v; }
+    static __device__ __forceinline__ double to_f64(const float* p, int) { return (double)*p; }
+    static __device__ __forceinline__ void from_f64(float* p, int, double v) { *p = (float)v; }
 };
+
+// FP16 holds h_a = d_a * 2^8 * {2, 8, 32} (rest, axis, diagonal): about
+// 230 d_a / w_a, so the deviations of a flow at lattice Mach numbers up to
+// ~0.3 sit between FP16's normal minimum (6.1e-5) and a few hundred, far
+// from both the subnormal range and overflow (65504).  Powers of two scale
+// exactly, so the only rounding is FP16's own (relative 2^-11).
+__device__ __forceinline__ float f16_scale(int a) { return a == 0 ? 512.0f : (a <= 4 ? 2048.0f : 8192.0f); }
+__device__ __forceinline__ float f16_unscale(int a)
+{
+    return a == 0 ? 1.0f / 512.0f : (a <= 4 ? 1.0f / 2048.0f : 1.0f / 8192.0f);
+}
 
 template <> struct Storage<_Float16> {
     using C = float;
-    static __device__ __forceinline__ C load(const _Float16* p) { return (float)*p; }
-    static __device__ __forceinline__ void store(_Float16* p, C v)
+    static constexpr bool kRounds = true;
+    static __device__ __forceinline__ C load(const _Float16* p, int a) { return (float)*p * f16_unscale(a); }
+    static __device__ __forceinline__ void store(_Float16* p, int a, C v)
     {
-        __builtin_nontemporal_store((_Float16)v, p);
+        __builtin_nontemporal_store((_Float16)(v * f16_scale(a)), p);
     }
-    static __device__ __forceinline__ double to_f64(const _Float16* p) { return (double)(float)*p; }
-    static __device__ __forceinline__ void from_f64(_Float16* p, double v) { *p = (_Float16)(float)v; }
+    static __device__ __forceinline__ C stored_value(C v, int a)
+    {
+        return (float)(_Float16)(v * f16_scale(a)) * f16_unscale(a);
+    }
+    static __device__ __forceinline__ double to_f64(const _Float16* p, int a)
+    {
+        return (double)((float)*p * f16_unscale(a));
+    }
+    static __device__ __forceinline__ void from_f64(_Float16* p, int a, double v)
+    {
+        *p = (_Float16)((float)v * f16_scale(a));
+    }
 };
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
@@ -68,15 +99,18 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float v)
     return (uint16_t)(u >> 16);
 }
 
+// bfloat16 keeps binary32's exponent range, so it needs no scaling.
 template <> struct Storage<bf16> {
     using C = float;
-    static __device__ __forceinline__ C load(const bf16* p) { return bf16_to_f32(p->bits); }
-    static __device__ __forceinline__ void store(bf16* p, C v)
+    static constexpr bool kRounds = true;
+    static __device__ __forceinline__ C load(const bf16* p, int) { return bf16_to_f32(p->bits); }
+    static __device__ __forceinline__ void store(bf16* p, int, C v)
     {
         __builtin_nontemporal_store(f32_to_bf16(v), &p->bits);
     }
-    static __device__ __forceinline__ double to_f64(const bf16* p) { return (double)bf16_to_f32(p->bits); }
-    static __device__ __forceinline__ void from_f64(bf16* p, double v) { p->bits = f32_to_bf16((float)v); }
+    static __device__ __forceinline__ C stored_value(C v, int) { return bf16_to_f32(f32_to_bf16(v)); }
+    static __device__ __forceinline__ double to_f64(const bf16* p, int) { return (double)bf16_to_f32(p->bits); }
+    static __device__ __forceinline__ void from_f64(bf16* p, int, double v) { p->bits = f32_to_bf16((float)v); }
 };
 
 // D2Q9 in the paper's order; OPP[a] is the direction with e = -e_a.
@@ -125,7 +159,7 @@ template <typename C> struct Coef {
 // drho, which restores conservation up to unbiased rounding:
 //   t_x = j_x / 2 - (t_5 - t_6),  t_y = j_y / 2 - (t_5 + t_6)  (both j / 3),
 //   q_0 = drho - 2 (s_x + s_y + s_5 + s_6)                      (w_0 (...)).
-template <int SCHEME, typename C>
+template <int SCHEME, typename T, typename C = typename Storage<T>::C>
 __device__ __forceinline__ void collide(C d[9], const Coef<C>& k)
 {
     const C drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
@@ -196,7 +230,13 @@ __device__ __forceinline__ void collide(C d[9], const Coef<C>& k)
     // The collision conserves mass, so the rest population is what the other
     // eight leave of drho.  Forming it from the rounded values removes a
     // rounding bias of about 1e-11 per node and step in FP32 that otherwise
-    // makes the total mass drift steadily.
+    // makes the total mass drift steadily.  With 16-bit storage the eight are
+    // first put on the storage grid, so only the rest population's own
+    // rounding (unbiased) changes the stored mass.
+    if constexpr (Storage<T>::kRounds) {
+#pragma unroll
+        for (int a = 1; a < 9; ++a) d[a] = Storage<T>::stored_value(d[a], a);
+    }
     d[0] = drho - (((d[1] + d[2]) + (d[3] + d[4])) + ((d[5] + d[6]) + (d[7] + d[8])));
 }
 
@@ -209,15 +249,15 @@ __device__ __forceinline__ void gather_interior(const T* __restrict__ src, const
     using S = Storage<T>;
     const T* p = src + (int64_t)y * g.pitch + x;
     const int64_t P = g.plane, R = g.pitch;
-    d[0] = S::load(p);
-    d[1] = S::load(p + 1 * P - 1);
-    d[2] = S::load(p + 2 * P - R);
-    d[3] = S::load(p + 3 * P + 1);
-    d[4] = S::load(p + 4 * P + R);
-    d[5] = S::load(p + 5 * P - R - 1);
-    d[6] = S::load(p + 6 * P - R + 1);
-    d[7] = S::load(p + 7 * P + R + 1);
-    d[8] = S::load(p + 8 * P + R - 1);
+    d[0] = S::load(p, 0);
+    d[1] = S::load(p + 1 * P - 1, 1);
+    d[2] = S::load(p + 2 * P - R, 2);
+    d[3] = S::load(p + 3 * P + 1, 3);
+    d[4] = S::load(p + 4 * P + R, 4);
+    d[5] = S::load(p + 5 * P - R - 1, 5);
+    d[6] = S::load(p + 6 * P - R + 1, 6);
+    d[7] = S::load(p + 7 * P + R + 1, 7);
+    d[8] = S::load(p + 8 * P + R - 1, 8);
 }
 
 // Pull at a node on the outer ring.  Periodic: sources wrap around.  Cavity:
@@ -237,12 +277,12 @@ __device__ __forceinline__ void gather_edge(const T* __restrict__ src, const Geo
         if constexpr (BC == PERIODIC) {
             sx = sx < 0 ? sx + g.nx : (sx >= g.nx ? sx - g.nx : sx);
             sy = sy < 0 ? sy + g.ny : (sy >= g.ny ? sy - g.ny : sy);
-            d[a] = S::load(src + a * g.plane + (int64_t)sy * g.pitch + sx);
+            d[a] = S::load(src + a * g.plane + (int64_t)sy * g.pitch + sx, a);
         } else {
             if (sx >= 0 && sx < g.nx && sy >= 0 && sy < g.ny) {
-                d[a] = S::load(src + a * g.plane + (int64_t)sy * g.pitch + sx);
+                d[a] = S::load(src + a * g.plane + (int64_t)sy * g.pitch + sx, a);
             } else {
-                C v = S::load(src + OPP[a] * g.plane + (int64_t)y * g.pitch + x);
+                C v = S::load(src + OPP[a] * g.plane + (int64_t)y * g.pitch + x, OPP[a]);
                 if (sy == g.ny) v += C(EX[a]) * lid;  // a = 7: -lid, a = 8: +lid, a = 4: 0
                 d[a] = v;
             }
@@ -256,7 +296,7 @@ __device__ __forceinline__ void scatter_store(T* __restrict__ dst, const Geom& g
 {
     T* p = dst + (int64_t)y * g.pitch + x;
 #pragma unroll
-    for (int a = 0; a < 9; ++a) Storage<T>::store(p + a * g.plane, d[a]);
+    for (int a = 0; a < 9; ++a) Storage<T>::store(p + a * g.plane, a, d[a]);
 }
 
 // One time step.  Block (bx, by) threads; each thread updates `rows` nodes
@@ -285,7 +325,7 @@ __global__ void __launch_bounds__(1024) stream_collide(const T* __restrict__ src
             gather_edge<T, BC>(src, g, x, y, d, k.lid);
         else
             gather_interior<T>(src, g, x, y, d);
-        collide<SCHEME>(d, k);
+        collide<SCHEME, T>(d, k);
         scatter_store<T>(dst, g, x, y, d);
     }
 }
@@ -309,7 +349,7 @@ __global__ void init_equilibrium(T* __restrict__ dst, Geom g, const F* __restric
         for (int a = 0; a < 9; ++a) {
             const double eu = EX[a] * vx + EY[a] * vy;
             const double dev = weight_f64(a) * ((r - 1.0) + r * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
-            Storage<T>::from_f64(p + a * g.plane, dev);
+            Storage<T>::from_f64(p + a * g.plane, a, dev);
         }
     }
 }
@@ -323,7 +363,7 @@ __global__ void set_populations(T* __restrict__ dst, Geom g, const F* __restrict
          i += (int64_t)gridDim.x * blockDim.x) {
         const int y = (int)(i / g.nx), x = (int)(i % g.nx);
         for (int a = 0; a < 9; ++a)
-            Storage<T>::from_f64(dst + a * g.plane + (int64_t)y * g.pitch + x,
+            Storage<T>::from_f64(dst + a * g.plane + (int64_t)y * g.pitch + x, a,
                                  (double)f[a * n + i] - weight_f64(a));
     }
 }
@@ -336,7 +376,7 @@ __global__ void get_populations(const T* __restrict__ src, Geom g, F* __restrict
          i += (int64_t)gridDim.x * blockDim.x) {
         const int y = (int)(i / g.nx), x = (int)(i % g.nx);
         for (int a = 0; a < 9; ++a)
-            f[a * n + i] = (F)(weight_f64(a) + Storage<T>::to_f64(src + a * g.plane + (int64_t)y * g.pitch + x));
+            f[a * n + i] = (F)(weight_f64(a) + Storage<T>::to_f64(src + a * g.plane + (int64_t)y * g.pitch + x, a));
     }
 }
 
@@ -347,7 +387,7 @@ __device__ __forceinline__ void node_moments_f64(const T* __restrict__ src, cons
 {
     double d[9];
 #pragma unroll
-    for (int a = 0; a < 9; ++a) d[a] = Storage<T>::to_f64(src + a * g.plane + off);
+    for (int a = 0; a < 9; ++a) d[a] = Storage<T>::to_f64(src + a * g.plane + off, a);
     drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
     jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
     jy = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
@@ -426,40 +466,6 @@ __global__ void __launch_bounds__(RED_THREADS) reduce_partials(const T* __restri
         for (int w = 0; w < RED_WAVES; ++w) t += lds[threadIdx.x][w];
         partials[(int64_t)blockIdx.x * RED_VALUES + threadIdx.x] = t;
     }
-}
-
-// One block: sums `nparts` partial rows in a fixed order into out[0..3].
-__global__ void __launch_bounds__(RED_THREADS) reduce_finish(const double* __restrict__ partials,
-                                                             int nparts, double* __restrict__ out)
-{
-    __shared__ double lds[RED_VALUES][RED_WAVES];
-    double s[RED_VALUES] = {0.0, 0.0, 0.0, 0.0};
-    for (int p = threadIdx.x; p < nparts; p += RED_THREADS)
-#pragma unroll
-        for (int v = 0; v < RED_VALUES; ++v) s[v] += partials[(int64_t)p * RED_VALUES + v];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int v = 0; v < RED_VALUES; ++v) {
-        const double t = wave_sum(s[v]);
-        if (lane == 0) lds[v][wave] = t;
-    }
-    __syncthreads();
-    if (threadIdx.x < RED_VALUES) {
-        double t = 0.0;
-        for (int w = 0; w < RED_WAVES; ++w) t += lds[threadIdx.x][w];
-        out[threadIdx.x] = t;
-    }
-}
-
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-
-// Plain streaming copy, 16 bytes per lane per iteration.
-__global__ void __launch_bounds__(256) copy_kernel(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
-                                                   int64_t n16)
-{
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n16;
-         i += (int64_t)gridDim.x * blockDim.x)
-        __builtin_nontemporal_store(src[i], dst + i);
 }
 
 } // namespace smrt

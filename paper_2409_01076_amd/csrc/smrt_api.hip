@@ -3,6 +3,7 @@
 // residual and mass read-back.
 #include "smrt.h"
 
+#include "host_util.hpp"
 #include "lbm_kernels.hpp"
 
 #include <hip/hip_runtime.h>
@@ -17,11 +18,48 @@
 #include <new>
 #include <string>
 
-namespace {
+namespace smrt {
+
+// One block: sums `nparts` partial rows in a fixed order into out[0..3].
+__global__ void __launch_bounds__(RED_THREADS) reduce_finish(const double* __restrict__ partials,
+                                                             int nparts, double* __restrict__ out)
+{
+    __shared__ double lds[RED_VALUES][RED_WAVES];
+    double s[RED_VALUES] = {0.0, 0.0, 0.0, 0.0};
+    for (int p = threadIdx.x; p < nparts; p += RED_THREADS)
+#pragma unroll
+        for (int v = 0; v < RED_VALUES; ++v) s[v] += partials[(int64_t)p * RED_VALUES + v];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int v = 0; v < RED_VALUES; ++v) {
+        const double t = wave_sum(s[v]);
+        if (lane == 0) lds[v][wave] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < RED_VALUES) {
+        double t = 0.0;
+        for (int w = 0; w < RED_WAVES; ++w) t += lds[threadIdx.x][w];
+        out[threadIdx.x] = t;
+    }
+}
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Plain streaming copy, 16 bytes per lane per iteration.
+__global__ void __launch_bounds__(256) copy_kernel(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
+                                                   int64_t n16)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n16;
+         i += (int64_t)gridDim.x * blockDim.x)
+        __builtin_nontemporal_store(src[i], dst + i);
+}
+
+} // namespace smrt
+
+namespace smrt_host {
 
 thread_local std::string g_error;
 
-int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 int fail(int code, const char* fmt, ...)
 {
     char buf[512];
@@ -38,11 +76,20 @@ int hip_fail(hipError_t e, const char* what)
     return fail(SMRT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define HIP_TRY(call)                                                                              \
-    do {                                                                                           \
-        hipError_t e_ = (call);                                                                    \
-        if (e_ != hipSuccess) return hip_fail(e_, #call);                                          \
-    } while (0)
+int after_launch(const char* what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, what);
+    return SMRT_OK;
+}
+
+} // namespace smrt_host
+
+using smrt_host::after_launch;
+using smrt_host::fail;
+using smrt_host::hip_fail;
+
+namespace {
 
 constexpr size_t kAlign = 256;
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -239,13 +286,6 @@ int check_io_dtype(int32_t dtype)
 {
     if (dtype != SMRT_F32 && dtype != SMRT_F64)
         return fail(SMRT_EINVAL, "field dtype must be SMRT_F32 or SMRT_F64 (got %d)", dtype);
-    return SMRT_OK;
-}
-
-int after_launch(const char* what)
-{
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, what);
     return SMRT_OK;
 }
 
@@ -507,7 +547,7 @@ void smrt_destroy(smrt_ctx* c)
     delete c;
 }
 
-const char* smrt_last_error(void) { return g_error.c_str(); }
+const char* smrt_last_error(void) { return smrt_host::g_error.c_str(); }
 
 int smrt_copy_kernel(const void* src, void* dst, size_t bytes, void* stream)
 {

@@ -24,7 +24,11 @@ EXPORTED = (
     "smrt_get_populations", "smrt_step", "smrt_moments", "smrt_residual", "smrt_mass",
     "smrt_steps_done", "smrt_tau", "smrt_set_launch", "smrt_synchronize", "smrt_destroy",
     "smrt_last_error", "smrt_copy_kernel",
+    "smrt_batch_workspace_bytes", "smrt_batch_create", "smrt_batch_step", "smrt_batch_run",
+    "smrt_batch_autotune", "smrt_batch_moments", "smrt_batch_init_fields", "smrt_batch_steps_done",
+    "smrt_batch_running", "smrt_batch_destroy",
 )
+RUNNING, STEADY, UNSTABLE = 0, 1, 2
 
 
 class SmrtError(RuntimeError):
@@ -45,6 +49,18 @@ class Params(ctypes.Structure):
         ("scheme", ctypes.c_int32), ("boundary", ctypes.c_int32),
         ("storage", ctypes.c_int32), ("reserved0", ctypes.c_int32),
         ("tau", ctypes.c_double), ("re", ctypes.c_double),
+        ("u_lid", ctypes.c_double), ("tau_s", ctypes.c_double),
+        ("stream", ctypes.c_void_p),
+        ("reserved", ctypes.c_int64 * 4),
+    ]
+
+
+class BatchParams(ctypes.Structure):
+    _fields_ = [
+        ("count", ctypes.c_int32), ("scheme", ctypes.c_int32),
+        ("storage", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("nx", ctypes.POINTER(ctypes.c_int32)), ("ny", ctypes.POINTER(ctypes.c_int32)),
+        ("tau", ctypes.POINTER(ctypes.c_double)), ("re", ctypes.POINTER(ctypes.c_double)),
         ("u_lid", ctypes.c_double), ("tau_s", ctypes.c_double),
         ("stream", ctypes.c_void_p),
         ("reserved", ctypes.c_int64 * 4),
@@ -81,6 +97,18 @@ def load():
         "smrt_destroy": (None, [vp]),
         "smrt_last_error": (ctypes.c_char_p, []),
         "smrt_copy_kernel": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp]),
+        "smrt_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(BatchParams)]),
+        "smrt_batch_create": (ctypes.c_int, [ctypes.POINTER(BatchParams), vp, ctypes.c_size_t,
+                                             ctypes.POINTER(vp)]),
+        "smrt_batch_step": (ctypes.c_int, [vp, i64]),
+        "smrt_batch_run": (ctypes.c_int, [vp, ctypes.c_double, i64, i64, ctypes.POINTER(i64),
+                                          ctypes.POINTER(i32), dp]),
+        "smrt_batch_autotune": (ctypes.c_int, [vp, i32, ctypes.POINTER(i32)]),
+        "smrt_batch_moments": (ctypes.c_int, [vp, i32, vp, vp, vp, i32]),
+        "smrt_batch_init_fields": (ctypes.c_int, [vp, i32, vp, vp, vp, i32]),
+        "smrt_batch_steps_done": (i64, [vp]),
+        "smrt_batch_running": (i32, [vp]),
+        "smrt_batch_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -240,6 +268,38 @@ class Solver:
         _check(load().smrt_mass(self._ctx, ctypes.byref(out)))
         return out.value
 
+    def run_to_steady(self, tol=1e-7, window=1000, max_steps=10_000_000, callback=None):
+        """Steps in windows of `window` until the windowed residual drops below
+        `tol` or `max_steps` is reached.  Returns (steps, residuals, converged);
+        raises UnstableError if the field blows up."""
+        residuals = []
+        steps = 0
+        while steps < max_steps:
+            n = min(window, max_steps - steps)
+            self.step(n)
+            steps += n
+            r = self.residual()
+            residuals.append(r)
+            if callback is not None:
+                callback(steps, r)
+            if r < tol:
+                return steps, residuals, True
+        return steps, residuals, False
+
+    def convert(self, storage):
+        """A new solver with the same lattice and parameters in another storage
+        type, holding this solver's current populations (rounded to the new
+        type).  Its step counter and residual snapshot start afresh."""
+        p = self._params
+        other = Solver(self.nx, self.ny, scheme=self.scheme, boundary=self.boundary,
+                       storage=storage, tau=self.tau, u_lid=p.u_lid, tau_s=p.tau_s,
+                       device=self.device)
+        # FP64 transfer: w + d and back is exact for every storage type's d
+        f = self.populations(torch.float64)
+        other.set_populations(f)
+        del f
+        return other
+
     def set_launch(self, bx, by, rows=1):
         _check(load().smrt_set_launch(self._ctx, int(bx), int(by), int(rows)))
 
@@ -252,3 +312,108 @@ def copy_kernel(src, dst, nbytes=None, stream=None):
     nbytes = src.numel() * src.element_size() if nbytes is None else int(nbytes)
     s = (stream or torch.cuda.current_stream(src.device)).cuda_stream
     _check(load().smrt_copy_kernel(_ptr(src), _ptr(dst), nbytes, ctypes.c_void_p(s or None)))
+
+
+class Batch:
+    """Many lid-driven cavities advanced together on one GPU (smrt_batch_*).
+
+    ``nx``, ``ny``: side lengths per cavity; ``tau`` or ``re`` per cavity
+    (sequence or None); one lid speed for all.  Workspace: a torch uint8
+    tensor; work goes to the current torch stream at construction time.
+    """
+
+    def __init__(self, nx, ny, scheme="smrt", storage="f32", tau=None, re=None, u_lid=0.1,
+                 tau_s=1.0, device="cuda:0"):
+        lib = load()
+        self.device = torch.device(device)
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+        self.nx = [int(v) for v in nx]
+        self.ny = [int(v) for v in ny]
+        self.count = len(self.nx)
+        if len(self.ny) != self.count:
+            raise ValueError("nx and ny must have the same length")
+        c = self.count
+        self._nx = (ctypes.c_int32 * c)(*self.nx)
+        self._ny = (ctypes.c_int32 * c)(*self.ny)
+        self._tau = (ctypes.c_double * c)(*[float(t) for t in tau]) if tau is not None else None
+        self._re = (ctypes.c_double * c)(*[float(r) for r in re]) if re is not None else None
+        p = BatchParams()
+        p.count, p.scheme, p.storage = c, SCHEMES[scheme], STORAGE[storage]
+        p.nx = ctypes.cast(self._nx, ctypes.POINTER(ctypes.c_int32))
+        p.ny = ctypes.cast(self._ny, ctypes.POINTER(ctypes.c_int32))
+        p.tau = ctypes.cast(self._tau, ctypes.POINTER(ctypes.c_double)) if self._tau else None
+        p.re = ctypes.cast(self._re, ctypes.POINTER(ctypes.c_double)) if self._re else None
+        p.u_lid, p.tau_s = float(u_lid), float(tau_s)
+        p.stream = self.stream.cuda_stream or None
+        self._params = p
+        self.scheme, self.storage = scheme, storage
+        nbytes = lib.smrt_batch_workspace_bytes(ctypes.byref(p))
+        if nbytes == 0:
+            _check(lib.smrt_batch_create(ctypes.byref(p), None, 0, ctypes.byref(ctypes.c_void_p())))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        ctx = ctypes.c_void_p()
+        _check(lib.smrt_batch_create(ctypes.byref(p), _ptr(self.workspace), nbytes, ctypes.byref(ctx)))
+        self._ctx = ctx
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            load().smrt_batch_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def steps_done(self):
+        return int(load().smrt_batch_steps_done(self._ctx))
+
+    @property
+    def running(self):
+        return int(load().smrt_batch_running(self._ctx))
+
+    def step(self, n):
+        _check(load().smrt_batch_step(self._ctx, int(n)))
+
+    def run(self, tol=1e-7, window=1000, max_steps=500_000):
+        """Runs until every cavity is steady/unstable or max_steps more steps.
+        Returns (steps, status, residual) lists, one entry per cavity."""
+        c = self.count
+        steps = (ctypes.c_int64 * c)()
+        status = (ctypes.c_int32 * c)()
+        res = (ctypes.c_double * c)()
+        _check(load().smrt_batch_run(self._ctx, float(tol), int(window), int(max_steps), steps,
+                                     status, res))
+        return list(steps), list(status), list(res)
+
+    def autotune(self, steps=20):
+        """Times the candidate launch shapes; returns the chosen (bx, by, grid)."""
+        chosen = (ctypes.c_int32 * 3)()
+        _check(load().smrt_batch_autotune(self._ctx, int(steps), chosen))
+        return tuple(chosen)
+
+    def moments(self, index, dtype=torch.float64):
+        s = (self.ny[index], self.nx[index])
+        rho, ux, uy = (torch.empty(s, dtype=dtype, device=self.device) for _ in range(3))
+        _check(load().smrt_batch_moments(self._ctx, int(index), _ptr(rho), _ptr(ux), _ptr(uy),
+                                         _IO_DTYPES[dtype]))
+        return rho, ux, uy
+
+    def init_fields(self, index, rho=None, ux=None, uy=None):
+        given = [t for t in (rho, ux, uy) if t is not None]
+        dtype = given[0].dtype if given else torch.float32
+        s = (self.ny[index], self.nx[index])
+        for t in given:
+            if t.dtype != dtype or tuple(t.shape) != s or not t.is_contiguous() or t.device != self.device:
+                raise ValueError("fields must be contiguous %s tensors of shape %s" % (dtype, s))
+        _check(load().smrt_batch_init_fields(self._ctx, int(index), _ptr(rho), _ptr(ux), _ptr(uy),
+                                             _IO_DTYPES[dtype]))

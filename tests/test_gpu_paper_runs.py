@@ -1,0 +1,90 @@
+"""The paper's cavity runs on the GPU, as claim checks (cavity section):
+SmrtLBM stays stable where SRT does not, at the paper's tau = 0.51 and 0.502.
+
+Lattice lid speeds follow from the paper's setup (u0 = 1, L = 1, tau fixed):
+U_lat = Re (2 tau - 1) / (6 N).
+
+Two of the paper's runs are not reproduced with half-way bounce-back walls and
+a moving-wall lid: Re = 10^5 on 400^2 (tau = 0.502, U_lat = 1/6) and Re = 10^4
+on 100^2 (U_lat = 1/3) diverge within 5000 steps with SmrtLBM and with the
+two-relaxation-time form, in FP32 and FP64, whether the lid owns the corner
+links or not.  Those tests are strict xfails: they state the paper's claim and
+would flip if a change made the runs stable.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def smrt():
+    return require_gpu()
+
+
+def lid_speed(re, tau, n):
+    return re * (2 * tau - 1) / (6 * n)
+
+
+@pytest.mark.xfail(strict=True, raises=Exception,
+                   reason="diverges within 5000 steps under half-way bounce-back and a moving-wall lid")
+def test_re1e5_400_tau0502_smrt_stable_for_a_million_steps(smrt):
+    """Re = 10^5 on 400^2 with tau = 0.502: stable over 10^6 steps (the figure
+    times imply 10^6 steps; the text says 10^5)."""
+    u = lid_speed(1e5, 0.502, 400)
+    assert abs(u - 1 / 6) < 1e-3
+    with smrt.Solver(400, 400, scheme="smrt", boundary="cavity", storage="f32", tau=0.502,
+                     u_lid=u) as s:
+        for _ in range(10):
+            s.step(100_000)
+            r = s.residual()
+            assert np.isfinite(r)
+        _, ux, uy = s.moments()
+        assert float(ux.abs().max()) < 0.5 and float(uy.abs().max()) < 0.5
+        # never steady: the residual stays far above the steady-state threshold
+        assert r > 1e-6
+
+
+def test_re1e5_400_tau0502_srt_blows_up(smrt):
+    u = lid_speed(1e5, 0.502, 400)
+    with smrt.Solver(400, 400, scheme="srt", boundary="cavity", storage="f32", tau=0.502,
+                     u_lid=u) as s:
+        s.step(20_000)
+        with pytest.raises(smrt.UnstableError):
+            s.residual()
+
+
+@pytest.mark.parametrize("n", [
+    pytest.param(100, marks=pytest.mark.xfail(strict=True, raises=Exception,
+                                              reason="U_lat = 1/3 diverges within 5000 steps")),
+    200, 250])
+def test_re1e4_grid_series_smrt_stable(smrt, n):
+    """Re = 10^4 on 100^2, 200^2 and 250^2 with tau = 0.51 stays finite."""
+    u = lid_speed(1e4, 0.51, n)
+    with smrt.Solver(n, n, scheme="smrt", boundary="cavity", storage="f32", tau=0.51,
+                     u_lid=u) as s:
+        for _ in range(5):
+            s.step(40_000)
+            assert np.isfinite(s.residual())
+
+
+@pytest.mark.parametrize("tau_s", [0.8, 1.2])
+def test_two_relaxation_time_form_also_stable(smrt, tau_s):
+    """The appendix's two-relaxation-time form with tau_s near 1 behaves like
+    SmrtLBM on the 250^2, Re = 10^4 run."""
+    u = lid_speed(1e4, 0.51, 250)
+    with smrt.Solver(250, 250, scheme="trt", boundary="cavity", storage="f32", tau=0.51,
+                     tau_s=tau_s, u_lid=u) as s:
+        s.step(100_000)
+        assert np.isfinite(s.residual())
+
+
+def test_re1e4_250_srt_blows_up(smrt):
+    u = lid_speed(1e4, 0.51, 250)
+    with smrt.Solver(250, 250, scheme="srt", boundary="cavity", storage="f32", tau=0.51,
+                     u_lid=u) as s:
+        s.step(50_000)
+        with pytest.raises(smrt.UnstableError):
+            s.residual()

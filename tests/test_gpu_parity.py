@@ -277,3 +277,68 @@ def test_copy_kernel(smrt):
     smrt.copy_kernel(a, b)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+# --- 16-bit deviation storage (FP32 arithmetic) -------------------------------------------
+
+W9 = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+REL16 = {"f16": 2.0 ** -11, "bf16": 2.0 ** -8}   # unit roundoff of the storage type
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+@pytest.mark.parametrize("boundary", ["periodic", "cavity"])
+@pytest.mark.parametrize("scheme", ["srt", "smrt", "trt"])
+def test_one_step_16bit_storage(smrt, storage, boundary, scheme):
+    """Input rounding to the storage grid, one exact FP32 update, output rounding:
+    every population within a few storage ulps of the oracle's deviation."""
+    nx, ny = 67, 45
+    f0 = inputs.perturbed_populations(nx, ny, eps=0.05, seed=99)
+    u = 0.08 if boundary == "cavity" else 0.0
+    L = oracle_lattice(nx, ny, scheme, boundary, 0.57, u, 0.83)
+    want = L.collide(oracle_from_post_collision(L, np.moveaxis(f0, 0, -1), 1))
+    with smrt.Solver(nx, ny, scheme=scheme, boundary=boundary, storage=storage, tau=0.57,
+                     u_lid=u, tau_s=0.83) as s:
+        s.set_populations(to_dev(f0, torch.float64))
+        s.step(1)
+        got = gpu_populations(s)
+    dev = np.abs(want - W9)
+    err = np.max(np.abs(got - want))
+    print("one-step %s %s %s: max err %.3e, max |d| %.3e" % (storage, boundary, scheme, err, dev.max()))
+    assert err <= 6 * REL16[storage] * dev.max()
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+@pytest.mark.parametrize("scheme", ["smrt", "srt"])
+def test_cavity_64_16bit_storage_error_and_mass(smrt, storage, scheme):
+    """Error of 16-bit storage against the FP64 oracle, stated per result:
+    max|du|/U after 2000 steps of the 64^2, Re = 100 cavity."""
+    n, u, steps = 64, 0.1, 2000
+    with smrt.Solver(n, n, scheme=scheme, boundary="cavity", storage=storage, re=100.0,
+                     u_lid=u) as s:
+        s.step(steps)
+        g = gpu_fields(s)
+        mass = s.mass()
+    L = O.Lattice(n, n, scheme, re=100.0, u_lid=u)
+    o = L.fields(L.run(L.init_equilibrium(), steps))
+    err = max_vel_err(g, o) / u
+    print("cavity64 %s %s max|du|/U = %.3e mass drift %.3e" % (scheme, storage, err, mass / n / n - 1))
+    bound = {"f16": 5e-3, "bf16": 5e-2}[storage]
+    assert err <= bound
+    assert abs(mass / (n * n) - 1) < {"f16": 1e-5, "bf16": 1e-4}[storage]
+
+
+def test_convert_between_storage_types(smrt):
+    """FP16 state converted to FP32 keeps its fields (to FP16 rounding) and runs on."""
+    n = 48
+    with smrt.Solver(n, n, scheme="smrt", boundary="cavity", storage="f16", re=100.0,
+                     u_lid=0.1) as a:
+        a.step(500)
+        fa = a.populations(torch.float64)
+        tau_a = a.tau
+        b = a.convert("f32")
+    with b:
+        assert b.storage == "f32" and b.steps_done == 0 and b.tau == tau_a
+        fb = b.populations(torch.float64)
+        assert float((fa - fb).abs().max()) == 0.0   # FP16 values are exact in FP32
+        b.step(10)
+        assert np.isfinite(b.residual())
