@@ -27,6 +27,20 @@ struct BatchLaunch {
     int bx, by;
 };
 
+// Descriptor tables are read-only during a launch and the same for a whole
+// workgroup; reading them through the constant address space lets the
+// compiler use scalar loads instead of vector loads plus a wait.
+typedef __attribute__((address_space(4))) const CavityDesc ConstDesc;
+
+__device__ __forceinline__ CavityDesc load_desc(const CavityDesc* cav, int i)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return ((ConstDesc*)cav)[i];
+#else
+    return cav[i]; // host pass: never executed
+#endif
+}
+
 template <typename C> __device__ __forceinline__ Coef<C> coef_of(const CavityDesc& c)
 {
     Coef<C> k;
@@ -50,7 +64,10 @@ __global__ void __launch_bounds__(1024) batch_stream_collide(const CavityDesc* _
     const int ntiles = *ntiles_p;
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int2 tt = tiles[t];
-        const CavityDesc c = cav[tt.x];
+        // The tile entry is the same for the whole workgroup: keep it, and the
+        // descriptor it points to, in scalar registers (scalar loads), so the
+        // population loads can be issued without waiting on vector loads.
+        const CavityDesc c = load_desc(cav, __builtin_amdgcn_readfirstlane(tt.x));
         Geom g;
         g.nx = c.nx;
         g.ny = c.ny;
@@ -60,11 +77,14 @@ __global__ void __launch_bounds__(1024) batch_stream_collide(const CavityDesc* _
         g.by = L.by;
         g.rows = 1;
         g.tiles_x = c.tiles_x;
-        const int x = (tt.y % c.tiles_x) * L.bx + threadIdx.x;
-        const int y = (tt.y / c.tiles_x) * L.by + threadIdx.y;
+        const int ti = __builtin_amdgcn_readfirstlane(tt.y);
+        const int x = (ti % c.tiles_x) * L.bx + threadIdx.x;
+        const int y = (ti / c.tiles_x) * L.by + threadIdx.y;
         if (x >= c.nx || y >= c.ny) continue;
-        const T* src = base + c.off[parity];
-        T* dst = base + c.off[parity ^ 1];
+        // select, not c.off[parity]: a runtime index into the local copy of
+        // the descriptor would put it in scratch memory
+        const T* src = base + (parity ? c.off[1] : c.off[0]);
+        T* dst = base + (parity ? c.off[0] : c.off[1]);
         C d[9];
         const bool edge = (x == 0) | (x == c.nx - 1) | (y == 0) | (y == c.ny - 1);
         if (edge)
@@ -94,15 +114,16 @@ __global__ void __launch_bounds__(1024) batch_reduce_partials(const CavityDesc* 
     const int nwaves = (blockDim.x * blockDim.y + 63) / 64;
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int2 tt = tiles[t];
-        const CavityDesc c = cav[tt.x];
-        const int x = (tt.y % c.tiles_x) * L.bx + threadIdx.x;
-        const int y = (tt.y / c.tiles_x) * L.by + threadIdx.y;
+        const CavityDesc c = load_desc(cav, __builtin_amdgcn_readfirstlane(tt.x));
+        const int ti = __builtin_amdgcn_readfirstlane(tt.y);
+        const int x = (ti % c.tiles_x) * L.bx + threadIdx.x;
+        const int y = (ti / c.tiles_x) * L.by + threadIdx.y;
         double s[RED_VALUES] = {0.0, 0.0, 0.0, 0.0};
         if (x < c.nx && y < c.ny) {
             Geom g;
             g.plane = c.plane;
             double drho, jx, jy;
-            node_moments_f64(base + c.off[parity], g, (int64_t)y * c.pitch + x, drho, jx, jy);
+            node_moments_f64(base + (parity ? c.off[1] : c.off[0]), g, (int64_t)y * c.pitch + x, drho, jx, jy);
             const double r = 1.0 + drho, vx = jx / r, vy = jy / r;
             double* sx = snap_base + c.snap + (int64_t)y * c.nx + x;
             double* sy = sx + (int64_t)c.nx * c.ny;

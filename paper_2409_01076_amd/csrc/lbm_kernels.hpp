@@ -264,28 +264,31 @@ __device__ __forceinline__ void gather_interior(const T* __restrict__ src, const
 // a source beyond a wall is replaced by the node's own opposite population
 // (half-way bounce-back); a link from the lid row (y = ny, corners included)
 // gains 6 w_a (e_a . u_lid), which is -u_lid/6 for a = 7, +u_lid/6 for a = 8
-// and 0 for a = 4.
+// and 0 for a = 4.  Branch-free: each direction selects its address and
+// issues one load, so the nine loads stay in flight together (a branch per
+// direction made the compiler wait on each load in turn).
 template <typename T, int BC>
 __device__ __forceinline__ void gather_edge(const T* __restrict__ src, const Geom& g, int x, int y,
                                             typename Storage<T>::C d[9], typename Storage<T>::C lid)
 {
     using S = Storage<T>;
     using C = typename Storage<T>::C;
+    const int own = y * g.pitch + x; // one plane never exceeds 2^31 elements
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         int sx = x - EX[a], sy = y - EY[a];
+        const T* plane_a = src + a * g.plane; // uniform per workgroup
         if constexpr (BC == PERIODIC) {
             sx = sx < 0 ? sx + g.nx : (sx >= g.nx ? sx - g.nx : sx);
             sy = sy < 0 ? sy + g.ny : (sy >= g.ny ? sy - g.ny : sy);
-            d[a] = S::load(src + a * g.plane + (int64_t)sy * g.pitch + sx, a);
+            d[a] = S::load(plane_a + (sy * g.pitch + sx), a);
         } else {
-            if (sx >= 0 && sx < g.nx && sy >= 0 && sy < g.ny) {
-                d[a] = S::load(src + a * g.plane + (int64_t)sy * g.pitch + sx, a);
-            } else {
-                C v = S::load(src + OPP[a] * g.plane + (int64_t)y * g.pitch + x, OPP[a]);
-                if (sy == g.ny) v += C(EX[a]) * lid;  // a = 7: -lid, a = 8: +lid, a = 4: 0
-                d[a] = v;
-            }
+            const T* plane_o = src + OPP[a] * g.plane;
+            const bool inside = (unsigned)sx < (unsigned)g.nx && (unsigned)sy < (unsigned)g.ny;
+            const T* p = inside ? plane_a + (sy * g.pitch + sx) : plane_o + own;
+            // a and OPP[a] share a weight class, hence a storage scale
+            const C v = S::load(p, a);
+            d[a] = (!inside && sy == g.ny) ? v + C(EX[a]) * lid : v;
         }
     }
 }
