@@ -251,6 +251,84 @@ int32_t smrt_batch_running(const smrt_batch* b);
 /* Frees what the library allocated (not the caller's workspace). NULL: no-op. */
 void smrt_batch_destroy(smrt_batch* b);
 
+/* ------------------------------------------------------------------------
+ * Warm-start network: a coordinate network that maps a node position and the
+ * Reynolds number to (rho, u, v) of the steady cavity flow, used to set the
+ * initial populations f = f^eq(rho, u) (Eq. feq-full) instead of the uniform
+ * cold start.  Inputs p = (x, y, s), with x, y the node centre over the side
+ * length and s = log(Re/100)/log(100).  Features: [x, y, s, sin(2 pi B p),
+ * cos(2 pi B p)] with the caller's fixed frequency matrix B (fourier x 3);
+ * then (layers - 1) SiLU layers of `width` and a linear output layer.
+ * Arithmetic: bfloat16 operands on the matrix cores with FP32 accumulation;
+ * FP32 master weights, biases, pre-activations and Adam state.
+ *
+ * Parameter layout (FP32, dense, what set/get_params and smrt_mlp_gradient
+ * use): for each layer l in order, W_l as [in_l][out_l] row-major, then b_l
+ * [out_l]; in_0 = 3 + 2 fourier, out_last = outputs.
+ * Row counts n of every call: a multiple of 64, at most max_batch.
+ * ------------------------------------------------------------------------ */
+
+typedef struct smrt_mlp_params {
+    int32_t inputs;     /* must be 3: (x, y, s)                           */
+    int32_t fourier;    /* frequencies in B, 0..64                        */
+    int32_t width;      /* hidden width, a multiple of 64 up to 1024      */
+    int32_t layers;     /* weight layers (hidden + output), 2..16         */
+    int32_t outputs;    /* 1..64                                          */
+    int32_t max_batch;  /* rows per call, a multiple of 64                */
+    void* stream;       /* hipStream_t, NULL for the default stream       */
+    int64_t reserved[4];/* must be 0                                      */
+} smrt_mlp_params;
+
+typedef struct smrt_mlp smrt_mlp;
+
+/* Number of FP32 parameters in the dense layout (0 if params are invalid). */
+size_t smrt_mlp_param_count(const smrt_mlp_params* p);
+
+/* Device workspace bytes (weights, Adam state, activations of max_batch rows). */
+size_t smrt_mlp_workspace_bytes(const smrt_mlp_params* p);
+
+/* Creates a network (dev_ws as for smrt_create).  Parameters must be set
+ * before use. */
+int smrt_mlp_create(const smrt_mlp_params* p, void* dev_ws, size_t ws_bytes, smrt_mlp** out);
+
+/* Loads parameters (device, dense layout) and the frequency matrix B
+ * (device, fourier x 3 FP32); resets the Adam state.  Asynchronous. */
+int smrt_mlp_set_params(smrt_mlp* m, const float* params, const float* fourier);
+
+/* Writes the FP32 master parameters (device, dense layout).  Asynchronous. */
+int smrt_mlp_get_params(smrt_mlp* m, float* params);
+
+/* out[n][outputs] (device FP32) for points[n][3] (device FP32).  Asynchronous. */
+int smrt_mlp_forward(smrt_mlp* m, const float* points, int32_t n, float* out);
+
+/* Gradient of the mean squared error sum (y - target)^2 / (n outputs) with
+ * respect to the parameters, into grad (device, dense layout); target is
+ * [n][outputs] (device FP32).  loss (host, may be NULL) receives the error
+ * (then the call synchronizes). */
+int smrt_mlp_gradient(smrt_mlp* m, const float* points, const float* target, int32_t n, float* grad,
+                      double* loss);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on the
+ * mean squared error of this batch.  loss as above. */
+int smrt_mlp_train_step(smrt_mlp* m, const float* points, const float* target, int32_t n, float lr,
+                        double* loss);
+
+/* Frees what the library allocated.  NULL: no-op. */
+void smrt_mlp_destroy(smrt_mlp* m);
+
+/* The network's matrix product on the matrix cores, exposed for checks and
+ * reuse: for each split s < splits,
+ *   C[s][m][n] = sum_{k in split s} opA(m, k) opB(k, n),
+ *   opA(m, k) = trans_a ? A[k lda + m] : A[m lda + k],
+ *   opB(k, n) = trans_b ? B[n ldb + k] : B[k ldb + n],
+ * A, B bfloat16 bit patterns (device), C FP32 (device, splits blocks of
+ * M x ldc).  M and N multiples of 64, K a multiple of 32 * splits; split s
+ * covers k in [s K/splits, (s+1) K/splits).  SMRT_EINVAL otherwise.
+ * Asynchronous on `stream`. */
+int smrt_gemm_bf16(const uint16_t* A, const uint16_t* B, float* C, int32_t M, int32_t N, int32_t K,
+                   int32_t lda, int32_t ldb, int32_t ldc, int32_t trans_a, int32_t trans_b,
+                   int32_t splits, void* stream);
+
 /* Bandwidth reference: copies `bytes` (a multiple of 16) from src to dst,
  * both device pointers 16-byte aligned, with a plain streaming copy kernel on
  * `stream`.  Used to calibrate byte counters and as the attainable read+write

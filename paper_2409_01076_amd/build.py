@@ -1,8 +1,9 @@
 """Compile the gfx950 HIP library ``libsmrt.so`` in-tree.
 
-Two translation units (``csrc/smrt_api.hip``: single lattices; ``csrc/smrt_batch.hip``:
-cavity batches; both include the kernel headers) are compiled by hipcc for
-gfx950 only and linked into one shared library.  Packed-FP32 instructions are disabled on
+Three translation units (``csrc/smrt_api.hip``: single lattices;
+``csrc/smrt_batch.hip``: cavity batches; ``csrc/smrt_mlp.hip``: the warm-start
+network) are compiled by hipcc for gfx950 only and linked into one shared
+library.  Packed-FP32 instructions are disabled on
 purpose (``-packed-fp32-ops``): the kernels are bandwidth-bound and gain
 nothing from them.
 """
@@ -12,7 +13,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRCS = [os.path.join(HERE, "csrc", f) for f in ("smrt_api.hip", "smrt_batch.hip")]
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("smrt_api.hip", "smrt_batch.hip", "smrt_mlp.hip")]
 LIB = os.path.join(HERE, "libsmrt.so")
 ARCH = "gfx950"
 

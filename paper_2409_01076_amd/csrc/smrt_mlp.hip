@@ -1,0 +1,417 @@
+// smrt_mlp.hip -- host runtime of the warm-start network (smrt_mlp_* in
+// include/smrt.h): parameter layout, forward pass, backward pass, Adam.
+//
+// Network: features [x, y, s, sin(2 pi B p), cos(2 pi B p)] -> (layers - 1)
+// SiLU layers of `width` -> linear layer of `outputs`.  Compute: bf16
+// operands on MFMA with FP32 accumulation; FP32 master weights, biases,
+// pre-activations and Adam state.
+#include "smrt.h"
+
+#include "host_util.hpp"
+#include "mlp_kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <vector>
+
+using smrt_host::after_launch;
+using smrt_host::fail;
+using smrt_host::hip_fail;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct MlpLayout {
+    int layers = 0, width = 0, nf = 0, outputs = 0, max_batch = 0;
+    int k0 = 0, k0_real = 0, n_last = 0;
+    std::vector<int> in, out, in_real, out_real; // padded and real sizes per layer
+    std::vector<size_t> w_off, b_off;             // offsets (floats) in the padded parameter block
+    size_t padded_params = 0, real_params = 0;
+    int max_splits = 64, chunks = 0;
+    // byte offsets in the workspace
+    size_t off_params = 0, off_wbf = 0, off_grad = 0, off_m = 0, off_v = 0, off_fourier = 0, off_x0 = 0,
+           off_z = 0, off_a = 0, off_c = 0, off_y = 0, off_dy = 0, off_dz0 = 0, off_dz1 = 0, off_wpart = 0,
+           off_bpart = 0, off_loss = 0, total = 0;
+    size_t z_stride = 0, a_stride = 0; // elements between hidden layers' Z / A arrays
+    int loss_blocks = 0;
+};
+
+int make_layout(const smrt_mlp_params* p, MlpLayout* out)
+{
+    if (!p) return fail(SMRT_EINVAL, "mlp params is NULL");
+    if (p->inputs != 3) return fail(SMRT_EINVAL, "the network takes 3 inputs (x, y, s), got %d", p->inputs);
+    if (p->fourier < 0 || p->fourier > 64) return fail(SMRT_EINVAL, "fourier features must be in 0..64");
+    if (p->width < 64 || p->width % 64 || p->width > 1024)
+        return fail(SMRT_EINVAL, "width must be a multiple of 64 in 64..1024 (got %d)", p->width);
+    if (p->layers < 2 || p->layers > 16) return fail(SMRT_EINVAL, "layers must be in 2..16 (got %d)", p->layers);
+    if (p->outputs < 1 || p->outputs > 64) return fail(SMRT_EINVAL, "outputs must be in 1..64");
+    if (p->max_batch < 64 || p->max_batch % 64 || p->max_batch > (1 << 24))
+        return fail(SMRT_EINVAL, "max_batch must be a positive multiple of 64 up to 2^24 (got %d)", p->max_batch);
+    for (int i = 0; i < 4; ++i)
+        if (p->reserved[i]) return fail(SMRT_EINVAL, "reserved[%d] must be 0", i);
+    MlpLayout L;
+    L.layers = p->layers;
+    L.width = p->width;
+    L.nf = p->fourier;
+    L.outputs = p->outputs;
+    L.max_batch = p->max_batch;
+    L.k0_real = 3 + 2 * p->fourier;
+    L.k0 = (int)round_up((size_t)L.k0_real, 64);
+    L.n_last = 64;
+    for (int l = 0; l < L.layers; ++l) {
+        L.in.push_back(l == 0 ? L.k0 : L.width);
+        L.in_real.push_back(l == 0 ? L.k0_real : L.width);
+        L.out.push_back(l == L.layers - 1 ? L.n_last : L.width);
+        L.out_real.push_back(l == L.layers - 1 ? L.outputs : L.width);
+    }
+    size_t pp = 0, rp = 0, max_w = 0;
+    for (int l = 0; l < L.layers; ++l) {
+        L.w_off.push_back(pp);
+        pp += (size_t)L.in[l] * L.out[l];
+        L.b_off.push_back(pp);
+        pp += L.out[l];
+        rp += (size_t)L.in_real[l] * L.out_real[l] + L.out_real[l];
+        max_w = std::max(max_w, (size_t)L.in[l] * L.out[l]);
+    }
+    L.padded_params = pp;
+    L.real_params = rp;
+    const size_t mb = (size_t)L.max_batch;
+    L.chunks = (int)((mb + 255) / 256);
+    L.loss_blocks = 1024;
+    const int hidden = L.layers - 1;
+    L.z_stride = mb * L.width;
+    L.a_stride = mb * L.width;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += round_up(bytes, kAlign);
+        return o;
+    };
+    L.off_params = take(pp * 4);
+    L.off_wbf = take(pp * 2);
+    L.off_grad = take(pp * 4);
+    L.off_m = take(pp * 4);
+    L.off_v = take(pp * 4);
+    L.off_fourier = take((size_t)std::max(1, L.nf) * 3 * 4);
+    L.off_x0 = take(mb * L.k0 * 2);
+    L.off_z = take((size_t)hidden * L.z_stride * 4);
+    L.off_a = take((size_t)hidden * L.a_stride * 2);
+    L.off_c = take(mb * std::max(L.width, L.n_last) * 4);
+    L.off_y = take(mb * L.outputs * 4);
+    L.off_dy = take(mb * L.n_last * 2);
+    L.off_dz0 = take(mb * L.width * 2);
+    L.off_dz1 = take(mb * L.width * 2);
+    L.off_wpart = take((size_t)L.max_splits * max_w * 4);
+    L.off_bpart = take((size_t)L.chunks * std::max(L.width, L.n_last) * 4);
+    L.off_loss = take((size_t)L.loss_blocks * 8);
+    L.total = off;
+    *out = std::move(L);
+    return SMRT_OK;
+}
+
+} // namespace
+
+struct smrt_mlp {
+    MlpLayout L;
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    bool owns_ws = false;
+    int64_t adam_steps = 0;
+    bool has_params = false;
+    std::vector<double> loss_host;
+
+    float* params() const { return reinterpret_cast<float*>(ws + L.off_params); }
+    uint16_t* wbf() const { return reinterpret_cast<uint16_t*>(ws + L.off_wbf); }
+    float* grad() const { return reinterpret_cast<float*>(ws + L.off_grad); }
+    float* adam_m() const { return reinterpret_cast<float*>(ws + L.off_m); }
+    float* adam_v() const { return reinterpret_cast<float*>(ws + L.off_v); }
+    float* fourier() const { return reinterpret_cast<float*>(ws + L.off_fourier); }
+    uint16_t* x0() const { return reinterpret_cast<uint16_t*>(ws + L.off_x0); }
+    float* z(int l) const { return reinterpret_cast<float*>(ws + L.off_z) + (size_t)l * L.z_stride; }
+    uint16_t* a(int l) const { return reinterpret_cast<uint16_t*>(ws + L.off_a) + (size_t)l * L.a_stride; }
+    float* cbuf() const { return reinterpret_cast<float*>(ws + L.off_c); }
+    float* y() const { return reinterpret_cast<float*>(ws + L.off_y); }
+    uint16_t* dy() const { return reinterpret_cast<uint16_t*>(ws + L.off_dy); }
+    uint16_t* dz(int i) const { return reinterpret_cast<uint16_t*>(ws + (i ? L.off_dz1 : L.off_dz0)); }
+    float* wpart() const { return reinterpret_cast<float*>(ws + L.off_wpart); }
+    float* bpart() const { return reinterpret_cast<float*>(ws + L.off_bpart); }
+    double* loss_part() const { return reinterpret_cast<double*>(ws + L.off_loss); }
+};
+
+namespace {
+
+int blocks_for(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 65536); }
+
+// C (+ split offset) = opA x opB through the MFMA kernel.
+int gemm(hipStream_t s, bool ta, bool tb, const uint16_t* A, const uint16_t* B, float* C, int M, int N, int K,
+         int lda, int ldb, int ldc, int splits)
+{
+    if (M % smrt::mlp::TM || N % smrt::mlp::TN || K % (smrt::mlp::TK * splits))
+        return fail(SMRT_EINVAL, "gemm shape %d x %d x %d (splits %d) not tile-aligned", M, N, K, splits);
+    dim3 grid(N / smrt::mlp::TN, M / smrt::mlp::TM, splits);
+    const int ks = K / splits;
+    if (!ta && !tb) smrt::mlp::gemm_bf16<false, false><<<grid, smrt::mlp::GEMM_THREADS, 0, s>>>(A, B, C, M, N, lda, ldb, ldc, ks);
+    else if (ta && !tb) smrt::mlp::gemm_bf16<true, false><<<grid, smrt::mlp::GEMM_THREADS, 0, s>>>(A, B, C, M, N, lda, ldb, ldc, ks);
+    else if (!ta && tb) smrt::mlp::gemm_bf16<false, true><<<grid, smrt::mlp::GEMM_THREADS, 0, s>>>(A, B, C, M, N, lda, ldb, ldc, ks);
+    else smrt::mlp::gemm_bf16<true, true><<<grid, smrt::mlp::GEMM_THREADS, 0, s>>>(A, B, C, M, N, lda, ldb, ldc, ks);
+    return after_launch("gemm_bf16");
+}
+
+int check_batch(const smrt_mlp* m, int32_t n)
+{
+    if (n < 64 || n % 64 || n > m->L.max_batch)
+        return fail(SMRT_EINVAL, "rows must be a multiple of 64 in 64..%d (got %d)", m->L.max_batch, n);
+    if (!m->has_params) return fail(SMRT_ESTATE, "parameters not set (smrt_mlp_set_params)");
+    return SMRT_OK;
+}
+
+// Forward pass over n rows of points; the output goes to `out` ([n][outputs]).
+int forward(smrt_mlp* m, const float* pts, int n, float* out)
+{
+    const MlpLayout& L = m->L;
+    hipStream_t s = m->stream;
+    smrt::mlp::features<<<blocks_for((int64_t)n * L.k0), 256, 0, s>>>(pts, m->fourier(), L.nf, n, L.k0, m->x0());
+    int rc = after_launch("features");
+    if (rc) return rc;
+    for (int l = 0; l < L.layers; ++l) {
+        const uint16_t* in = l == 0 ? m->x0() : m->a(l - 1);
+        const int K = L.in[l], N = L.out[l];
+        rc = gemm(s, false, false, in, m->wbf() + L.w_off[l], m->cbuf(), n, N, K, K, N, N, 1);
+        if (rc) return rc;
+        const float* b = m->params() + L.b_off[l];
+        if (l < L.layers - 1)
+            smrt::mlp::bias_act<<<blocks_for((int64_t)n * N), 256, 0, s>>>(m->cbuf(), b, n, N, 1, m->z(l), m->a(l), 0,
+                                                                          nullptr);
+        else
+            smrt::mlp::bias_act<<<blocks_for((int64_t)n * N), 256, 0, s>>>(m->cbuf(), b, n, N, 0, nullptr, nullptr,
+                                                                          L.outputs, out);
+        rc = after_launch("bias_act");
+        if (rc) return rc;
+    }
+    return SMRT_OK;
+}
+
+int splits_for(int n)
+{
+    int s = 64;
+    while (s > 1 && (n % (32 * s) || n / s < 256)) s >>= 1;
+    return s;
+}
+
+// Backward pass after forward() wrote m->y(): fills m->grad() (padded layout)
+// and, when loss != NULL, the mean squared error (synchronizes).
+int backward(smrt_mlp* m, const float* target, int n, double* loss)
+{
+    const MlpLayout& L = m->L;
+    hipStream_t s = m->stream;
+    smrt::mlp::mse_grad<<<L.loss_blocks, 256, 0, s>>>(m->y(), target, n, L.outputs, L.n_last, m->dy(),
+                                                      m->loss_part());
+    int rc = after_launch("mse_grad");
+    if (rc) return rc;
+    const int splits = splits_for(n);
+    const uint16_t* dcur = m->dy();
+    int flip = 0;
+    for (int l = L.layers - 1; l >= 0; --l) {
+        const uint16_t* in = l == 0 ? m->x0() : m->a(l - 1);
+        const int K = L.in[l], N = L.out[l];
+        // dW_l = in^T dZ_l, split over the rows, then summed in split order
+        rc = gemm(s, true, false, in, dcur, m->wpart(), K, N, n, K, N, N, splits);
+        if (rc) return rc;
+        smrt::mlp::column_sums<float><<<(K * N + 255) / 256, 256, 0, s>>>(m->wpart(), splits, K * N, (int64_t)K * N,
+                                                                         m->grad() + L.w_off[l]);
+        // db_l = column sums of dZ_l
+        const int chunks = (n + 255) / 256;
+        smrt::mlp::column_sums_chunked<uint16_t><<<dim3((N + 255) / 256, chunks), 256, 0, s>>>(dcur, n, N, N, 256,
+                                                                                             m->bpart());
+        smrt::mlp::column_sums<float><<<(N + 255) / 256, 256, 0, s>>>(m->bpart(), chunks, N, N,
+                                                                     m->grad() + L.b_off[l]);
+        rc = after_launch("weight gradients");
+        if (rc) return rc;
+        if (l == 0) break;
+        // dA_{l-1} = dZ_l W_l^T, then dZ_{l-1} = dA_{l-1} silu'(Z_{l-1})
+        rc = gemm(s, false, true, dcur, m->wbf() + L.w_off[l], m->cbuf(), n, K, N, N, N, K, 1);
+        if (rc) return rc;
+        uint16_t* dnext = m->dz(flip);
+        flip ^= 1;
+        smrt::mlp::silu_backward<<<blocks_for((int64_t)n * K), 256, 0, s>>>(m->cbuf(), m->z(l - 1), (int64_t)n * K,
+                                                                            dnext);
+        rc = after_launch("silu_backward");
+        if (rc) return rc;
+        dcur = dnext;
+    }
+    if (loss) {
+        m->loss_host.resize(L.loss_blocks);
+        HIP_TRY(hipMemcpyAsync(m->loss_host.data(), m->loss_part(), L.loss_blocks * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        double acc = 0.0;
+        for (double v : m->loss_host) acc += v;
+        *loss = acc / ((double)n * L.outputs);
+    }
+    return SMRT_OK;
+}
+
+// Real (dense) <-> padded parameter layout, one layer at a time.
+int convert_params(smrt_mlp* m, const float* src, float* dst, int to_padded)
+{
+    const MlpLayout& L = m->L;
+    size_t real = 0;
+    for (int l = 0; l < L.layers; ++l) {
+        const int rows = L.in_real[l], cols = L.out_real[l];
+        const float* s_w = to_padded ? src + real : src + L.w_off[l];
+        float* d_w = to_padded ? dst + L.w_off[l] : dst + real;
+        smrt::mlp::pad_copy<<<blocks_for((int64_t)rows * cols), 256, 0, m->stream>>>(s_w, d_w, rows, cols, L.out[l],
+                                                                                    to_padded);
+        real += (size_t)rows * cols;
+        const float* s_b = to_padded ? src + real : src + L.b_off[l];
+        float* d_b = to_padded ? dst + L.b_off[l] : dst + real;
+        smrt::mlp::pad_copy<<<blocks_for(cols), 256, 0, m->stream>>>(s_b, d_b, 1, cols, cols, to_padded);
+        real += cols;
+    }
+    return after_launch("pad_copy");
+}
+
+} // namespace
+
+extern "C" {
+
+size_t smrt_mlp_param_count(const smrt_mlp_params* p)
+{
+    MlpLayout L;
+    if (make_layout(p, &L) != SMRT_OK) return 0;
+    return L.real_params;
+}
+
+size_t smrt_mlp_workspace_bytes(const smrt_mlp_params* p)
+{
+    MlpLayout L;
+    if (make_layout(p, &L) != SMRT_OK) return 0;
+    return L.total;
+}
+
+int smrt_mlp_create(const smrt_mlp_params* p, void* dev_ws, size_t ws_bytes, smrt_mlp** out)
+{
+    try {
+        if (!out) return fail(SMRT_EINVAL, "out is NULL");
+        *out = nullptr;
+        MlpLayout L;
+        int rc = make_layout(p, &L);
+        if (rc) return rc;
+        if (dev_ws && ws_bytes < L.total)
+            return fail(SMRT_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, L.total);
+        if (dev_ws && (reinterpret_cast<uintptr_t>(dev_ws) % kAlign))
+            return fail(SMRT_EINVAL, "workspace must be %zu-byte aligned", kAlign);
+        smrt_mlp* m = new (std::nothrow) smrt_mlp;
+        if (!m) return fail(SMRT_ENOMEM, "out of host memory");
+        m->L = std::move(L);
+        m->stream = static_cast<hipStream_t>(p->stream);
+        if (dev_ws) {
+            m->ws = static_cast<char*>(dev_ws);
+        } else {
+            hipError_t e = hipMalloc(reinterpret_cast<void**>(&m->ws), m->L.total);
+            if (e != hipSuccess) {
+                delete m;
+                return fail(SMRT_ENOMEM, "hipMalloc(%zu): %s", m->L.total, hipGetErrorString(e));
+            }
+            m->owns_ws = true;
+        }
+        *out = m;
+        return SMRT_OK;
+    } catch (...) {
+        return fail(SMRT_ENOMEM, "unexpected host exception in smrt_mlp_create");
+    }
+}
+
+int smrt_mlp_set_params(smrt_mlp* m, const float* params, const float* fourier)
+{
+    if (!m || !params) return fail(SMRT_EINVAL, "network or parameters is NULL");
+    if (m->L.nf > 0 && !fourier) return fail(SMRT_EINVAL, "Fourier frequencies are required");
+    const MlpLayout& L = m->L;
+    const size_t pb = L.padded_params * sizeof(float);
+    HIP_TRY(hipMemsetAsync(m->params(), 0, pb, m->stream));
+    HIP_TRY(hipMemsetAsync(m->adam_m(), 0, pb, m->stream));
+    HIP_TRY(hipMemsetAsync(m->adam_v(), 0, pb, m->stream));
+    HIP_TRY(hipMemsetAsync(m->grad(), 0, pb, m->stream));
+    if (L.nf > 0)
+        HIP_TRY(hipMemcpyAsync(m->fourier(), fourier, (size_t)L.nf * 3 * sizeof(float), hipMemcpyDeviceToDevice,
+                               m->stream));
+    int rc = convert_params(m, params, m->params(), 1);
+    if (rc) return rc;
+    smrt::mlp::to_bf16<<<blocks_for((int64_t)L.padded_params), 256, 0, m->stream>>>(
+        m->params(), (int64_t)L.padded_params, m->wbf());
+    rc = after_launch("to_bf16");
+    if (rc) return rc;
+    m->adam_steps = 0;
+    m->has_params = true;
+    return SMRT_OK;
+}
+
+int smrt_mlp_get_params(smrt_mlp* m, float* params)
+{
+    if (!m || !params) return fail(SMRT_EINVAL, "network or output is NULL");
+    if (!m->has_params) return fail(SMRT_ESTATE, "parameters not set");
+    return convert_params(m, m->params(), params, 0);
+}
+
+int smrt_mlp_forward(smrt_mlp* m, const float* points, int32_t n, float* out)
+{
+    if (!m || !points || !out) return fail(SMRT_EINVAL, "network, points or output is NULL");
+    int rc = check_batch(m, n);
+    if (rc) return rc;
+    return forward(m, points, n, out);
+}
+
+int smrt_mlp_gradient(smrt_mlp* m, const float* points, const float* target, int32_t n, float* grad,
+                      double* loss)
+{
+    if (!m || !points || !target || !grad) return fail(SMRT_EINVAL, "network, points, target or grad is NULL");
+    int rc = check_batch(m, n);
+    if (rc) return rc;
+    rc = forward(m, points, n, m->y());
+    if (!rc) rc = backward(m, target, n, loss);
+    if (!rc) rc = convert_params(m, m->grad(), grad, 0);
+    return rc;
+}
+
+int smrt_mlp_train_step(smrt_mlp* m, const float* points, const float* target, int32_t n, float lr, double* loss)
+{
+    if (!m || !points || !target) return fail(SMRT_EINVAL, "network, points or target is NULL");
+    if (!(lr > 0.0f) || !std::isfinite(lr)) return fail(SMRT_EINVAL, "learning rate must be positive");
+    int rc = check_batch(m, n);
+    if (rc) return rc;
+    rc = forward(m, points, n, m->y());
+    if (!rc) rc = backward(m, target, n, loss);
+    if (rc) return rc;
+    m->adam_steps += 1;
+    const double t = (double)m->adam_steps;
+    const float lr_t = (float)(lr * std::sqrt(1.0 - std::pow(0.999, t)) / (1.0 - std::pow(0.9, t)));
+    smrt::mlp::adam<<<blocks_for((int64_t)m->L.padded_params), 256, 0, m->stream>>>(
+        m->params(), m->grad(), m->adam_m(), m->adam_v(), (int64_t)m->L.padded_params, lr_t, m->wbf());
+    return after_launch("adam");
+}
+
+int smrt_gemm_bf16(const uint16_t* A, const uint16_t* B, float* C, int32_t M, int32_t N, int32_t K, int32_t lda,
+                   int32_t ldb, int32_t ldc, int32_t trans_a, int32_t trans_b, int32_t splits, void* stream)
+{
+    if (!A || !B || !C) return fail(SMRT_EINVAL, "gemm operands must not be NULL");
+    if (M <= 0 || N <= 0 || K <= 0 || splits < 1 || splits > 4096)
+        return fail(SMRT_EINVAL, "gemm sizes must be positive (M %d N %d K %d splits %d)", M, N, K, splits);
+    if (lda < (trans_a ? M : K) || ldb < (trans_b ? K : N) || ldc < N)
+        return fail(SMRT_EINVAL, "gemm leading dimensions too small");
+    return gemm(static_cast<hipStream_t>(stream), trans_a != 0, trans_b != 0, A, B, C, M, N, K, lda, ldb, ldc, splits);
+}
+
+void smrt_mlp_destroy(smrt_mlp* m)
+{
+    if (!m) return;
+    (void)hipStreamSynchronize(m->stream);
+    if (m->owns_ws && m->ws) (void)hipFree(m->ws);
+    delete m;
+}
+
+} // extern "C"

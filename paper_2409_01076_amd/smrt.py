@@ -27,6 +27,9 @@ EXPORTED = (
     "smrt_batch_workspace_bytes", "smrt_batch_create", "smrt_batch_step", "smrt_batch_run",
     "smrt_batch_autotune", "smrt_batch_moments", "smrt_batch_init_fields", "smrt_batch_steps_done",
     "smrt_batch_running", "smrt_batch_destroy",
+    "smrt_mlp_param_count", "smrt_mlp_workspace_bytes", "smrt_mlp_create", "smrt_mlp_set_params",
+    "smrt_mlp_get_params", "smrt_mlp_forward", "smrt_mlp_gradient", "smrt_mlp_train_step",
+    "smrt_mlp_destroy", "smrt_gemm_bf16",
 )
 RUNNING, STEADY, UNSTABLE = 0, 1, 2
 
@@ -62,6 +65,15 @@ class BatchParams(ctypes.Structure):
         ("nx", ctypes.POINTER(ctypes.c_int32)), ("ny", ctypes.POINTER(ctypes.c_int32)),
         ("tau", ctypes.POINTER(ctypes.c_double)), ("re", ctypes.POINTER(ctypes.c_double)),
         ("u_lid", ctypes.c_double), ("tau_s", ctypes.c_double),
+        ("stream", ctypes.c_void_p),
+        ("reserved", ctypes.c_int64 * 4),
+    ]
+
+
+class MlpParams(ctypes.Structure):
+    _fields_ = [
+        ("inputs", ctypes.c_int32), ("fourier", ctypes.c_int32), ("width", ctypes.c_int32),
+        ("layers", ctypes.c_int32), ("outputs", ctypes.c_int32), ("max_batch", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
         ("reserved", ctypes.c_int64 * 4),
     ]
@@ -109,6 +121,17 @@ def load():
         "smrt_batch_steps_done": (i64, [vp]),
         "smrt_batch_running": (i32, [vp]),
         "smrt_batch_destroy": (None, [vp]),
+        "smrt_mlp_param_count": (ctypes.c_size_t, [ctypes.POINTER(MlpParams)]),
+        "smrt_mlp_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(MlpParams)]),
+        "smrt_mlp_create": (ctypes.c_int, [ctypes.POINTER(MlpParams), vp, ctypes.c_size_t,
+                                           ctypes.POINTER(vp)]),
+        "smrt_mlp_set_params": (ctypes.c_int, [vp, vp, vp]),
+        "smrt_mlp_get_params": (ctypes.c_int, [vp, vp]),
+        "smrt_mlp_forward": (ctypes.c_int, [vp, vp, i32, vp]),
+        "smrt_mlp_gradient": (ctypes.c_int, [vp, vp, vp, i32, vp, dp]),
+        "smrt_mlp_train_step": (ctypes.c_int, [vp, vp, vp, i32, ctypes.c_float, dp]),
+        "smrt_mlp_destroy": (None, [vp]),
+        "smrt_gemm_bf16": (ctypes.c_int, [vp, vp, vp, i32, i32, i32, i32, i32, i32, i32, i32, i32, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -417,3 +440,102 @@ class Batch:
                 raise ValueError("fields must be contiguous %s tensors of shape %s" % (dtype, s))
         _check(load().smrt_batch_init_fields(self._ctx, int(index), _ptr(rho), _ptr(ux), _ptr(uy),
                                              _IO_DTYPES[dtype]))
+
+
+class MLP:
+    """The warm-start coordinate network (smrt_mlp_*): points (x, y, s) ->
+    outputs, bf16 matrix-core arithmetic with FP32 accumulation.  All tensors
+    are float32 on the device; row counts must be multiples of 64."""
+
+    def __init__(self, fourier=16, width=128, layers=5, outputs=3, max_batch=65536,
+                 device="cuda:0"):
+        lib = load()
+        self.device = torch.device(device)
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+        p = MlpParams()
+        p.inputs, p.fourier, p.width, p.layers, p.outputs = 3, fourier, width, layers, outputs
+        p.max_batch = max_batch
+        p.stream = self.stream.cuda_stream or None
+        self._params = p
+        self.fourier, self.width, self.layers, self.outputs = fourier, width, layers, outputs
+        self.max_batch = max_batch
+        self.param_count = int(lib.smrt_mlp_param_count(ctypes.byref(p)))
+        nbytes = lib.smrt_mlp_workspace_bytes(ctypes.byref(p))
+        if nbytes == 0:
+            _check(lib.smrt_mlp_create(ctypes.byref(p), None, 0, ctypes.byref(ctypes.c_void_p())))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        ctx = ctypes.c_void_p()
+        _check(lib.smrt_mlp_create(ctypes.byref(p), _ptr(self.workspace), nbytes, ctypes.byref(ctx)))
+        self._ctx = ctx
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            load().smrt_mlp_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _f32(self, t, shape=None):
+        if t.dtype != torch.float32 or t.device != self.device or not t.is_contiguous():
+            raise ValueError("expected a contiguous float32 tensor on %s" % self.device)
+        if shape is not None and tuple(t.shape) != tuple(shape):
+            raise ValueError("expected shape %s, got %s" % (tuple(shape), tuple(t.shape)))
+        return t
+
+    def set_params(self, params, fourier_matrix):
+        self._f32(params, (self.param_count,))
+        self._f32(fourier_matrix, (self.fourier, 3))
+        _check(load().smrt_mlp_set_params(self._ctx, _ptr(params), _ptr(fourier_matrix)))
+
+    def get_params(self):
+        out = torch.empty(self.param_count, dtype=torch.float32, device=self.device)
+        _check(load().smrt_mlp_get_params(self._ctx, _ptr(out)))
+        return out
+
+    def forward(self, points, out=None):
+        n = points.shape[0]
+        self._f32(points, (n, 3))
+        if out is None:
+            out = torch.empty((n, self.outputs), dtype=torch.float32, device=self.device)
+        _check(load().smrt_mlp_forward(self._ctx, _ptr(points), int(n), _ptr(self._f32(out, (n, self.outputs)))))
+        return out
+
+    def gradient(self, points, target):
+        n = points.shape[0]
+        grad = torch.empty(self.param_count, dtype=torch.float32, device=self.device)
+        loss = ctypes.c_double()
+        _check(load().smrt_mlp_gradient(self._ctx, _ptr(self._f32(points, (n, 3))),
+                                        _ptr(self._f32(target, (n, self.outputs))), int(n), _ptr(grad),
+                                        ctypes.byref(loss)))
+        return loss.value, grad
+
+    def train_step(self, points, target, lr, want_loss=False):
+        n = points.shape[0]
+        loss = ctypes.c_double() if want_loss else None
+        _check(load().smrt_mlp_train_step(self._ctx, _ptr(self._f32(points, (n, 3))),
+                                          _ptr(self._f32(target, (n, self.outputs))), int(n),
+                                          float(lr), ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+
+def gemm_bf16(a_bits, b_bits, m, n, k, lda, ldb, ldc, trans_a=False, trans_b=False, splits=1,
+              out=None):
+    """C (splits x m x ldc, float32) from bf16 bit patterns held in int16 tensors."""
+    if out is None:
+        out = torch.empty((splits, m, ldc), dtype=torch.float32, device=a_bits.device)
+    s = torch.cuda.current_stream(a_bits.device).cuda_stream
+    _check(load().smrt_gemm_bf16(_ptr(a_bits), _ptr(b_bits), _ptr(out), int(m), int(n), int(k),
+                                 int(lda), int(ldb), int(ldc), int(bool(trans_a)), int(bool(trans_b)),
+                                 int(splits), ctypes.c_void_p(s or None)))
+    return out

@@ -1,0 +1,146 @@
+"""The warm-start network's GPU kernels: the bf16 MFMA product against an FP64
+product of the same bf16 values, the forward pass and the gradients against the
+FP64 CPU reference (oracle/mlp_oracle.py), and training that reduces the loss."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from gpu_util import require_gpu, torch
+from oracle import mlp_oracle as M
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def smrt():
+    return require_gpu()
+
+
+def bf16_round(a):
+    """Round-to-nearest-even to bfloat16, returned as float64."""
+    a = np.ascontiguousarray(a, np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def make_net(rng, fourier=16, width=128, layers=5, outputs=3):
+    dims = M.layer_dims(fourier, width, layers, outputs)
+    params = []
+    for i, o in dims:
+        params.append(rng.normal(0, np.sqrt(2.0 / i), size=(i, o)).ravel())
+        params.append(rng.normal(0, 0.05, size=o))
+    return dims, np.concatenate(params), rng.normal(0, 2.0, size=(fourier, 3))
+
+
+def test_forward_matches_oracle(smrt):
+    rng = np.random.default_rng(1)
+    dims, params, B = make_net(rng)
+    pts = rng.uniform(0, 1, size=(512, 3))
+    with smrt.MLP(max_batch=1024) as net:
+        net.set_params(torch.tensor(params, dtype=torch.float32, device="cuda:0"),
+                       torch.tensor(B, dtype=torch.float32, device="cuda:0"))
+        assert np.array_equal(net.get_params().cpu().numpy(), params.astype(np.float32))
+        y = net.forward(torch.tensor(pts, dtype=torch.float32, device="cuda:0")).cpu().numpy()
+    want, _ = M.forward(params.astype(np.float32), B.astype(np.float32), pts.astype(np.float32), dims)
+    rel = np.linalg.norm(y - want) / np.linalg.norm(want)
+    print("forward rel L2 error vs FP64: %.3e" % rel)
+    assert rel < 2e-2
+
+
+def test_gradient_matches_oracle(smrt):
+    rng = np.random.default_rng(2)
+    dims, params, B = make_net(rng)
+    n = 1024
+    pts = rng.uniform(0, 1, size=(n, 3)).astype(np.float32)
+    tgt = rng.normal(0, 0.5, size=(n, 3)).astype(np.float32)
+    with smrt.MLP(max_batch=n) as net:
+        net.set_params(torch.tensor(params, dtype=torch.float32, device="cuda:0"),
+                       torch.tensor(B, dtype=torch.float32, device="cuda:0"))
+        loss, g = net.gradient(torch.tensor(pts, device="cuda:0"), torch.tensor(tgt, device="cuda:0"))
+        g = g.cpu().numpy().astype(np.float64)
+    want_loss, want = M.loss_and_grad(params.astype(np.float32), B.astype(np.float32), pts, tgt, dims)
+    rel = np.linalg.norm(g - want) / np.linalg.norm(want)
+    cos = g @ want / (np.linalg.norm(g) * np.linalg.norm(want))
+    print("gradient rel L2 error %.3e, cosine %.6f, loss %.6f vs %.6f" % (rel, cos, loss, want_loss))
+    assert abs(loss / want_loss - 1) < 1e-2
+    assert rel < 3e-2 and cos > 0.9995
+
+
+def to_bf16_bits(a):
+    """float array of bf16-exact values -> int16 tensor of their bit patterns."""
+    u = np.ascontiguousarray(a, np.float32).view(np.uint32)
+    assert np.all((u & 0xFFFF) == 0), "values must be exact in bfloat16"
+    return torch.tensor((u >> 16).astype(np.uint16).view(np.int16), device="cuda:0")
+
+
+@pytest.mark.parametrize("ta", [False, True])
+@pytest.mark.parametrize("tb", [False, True])
+@pytest.mark.parametrize("m,n,k,splits", [(64, 64, 32, 1), (128, 192, 96, 1), (192, 128, 512, 4),
+                                          (64, 64, 2048, 64)])
+def test_gemm_bf16_exact(smrt, ta, tb, m, n, k, splits):
+    """Integer-valued bf16 operands: every FP32 partial sum is exact, so the
+    matrix-core product must equal the FP64 product bit for bit (all four
+    transposition cases, split-K, ragged leading dimensions)."""
+    rng = np.random.default_rng(m * 7 + n + k)
+    A = rng.integers(-8, 9, size=(m, k)).astype(np.float64)
+    Bm = rng.integers(-8, 9, size=(k, n)).astype(np.float64)
+    lda = (m if ta else k) + 16
+    ldb = (k if tb else n) + 32
+    a_store = np.zeros(((k if ta else m), lda))
+    b_store = np.zeros(((n if tb else k), ldb))
+    if ta:
+        a_store[:, :m] = A.T
+    else:
+        a_store[:, :k] = A
+    if tb:
+        b_store[:, :k] = Bm.T
+    else:
+        b_store[:, :n] = Bm
+    C = smrt.gemm_bf16(to_bf16_bits(a_store), to_bf16_bits(b_store), m, n, k, lda, ldb, n + 64,
+                       trans_a=ta, trans_b=tb, splits=splits).cpu().numpy()
+    ks = k // splits
+    for sidx in range(splits):
+        want = A[:, sidx * ks:(sidx + 1) * ks] @ Bm[sidx * ks:(sidx + 1) * ks, :]
+        assert np.array_equal(C[sidx][:, :n], want)
+
+
+def test_gemm_bf16_rejects_unaligned(smrt):
+    z = torch.zeros(64 * 64, dtype=torch.int16, device="cuda:0")
+    with pytest.raises(smrt.SmrtError):
+        smrt.gemm_bf16(z, z, 64, 64, 48, 64, 64, 64)      # K not a multiple of 32
+    with pytest.raises(smrt.SmrtError):
+        smrt.gemm_bf16(z, z, 32, 64, 32, 64, 64, 64)      # M not a multiple of 64
+
+
+def test_training_reduces_loss(smrt):
+    rng = np.random.default_rng(5)
+    dims, params, B = make_net(rng)
+    n = 4096
+    pts = rng.uniform(0, 1, size=(n, 3)).astype(np.float32)
+    x, y, s = pts[:, 0], pts[:, 1], pts[:, 2]
+    tgt = np.stack([np.sin(np.pi * x) * np.sin(np.pi * y) * (1 + s), np.cos(2 * x) * y, x * y - s],
+                   axis=1).astype(np.float32)
+    P, T = torch.tensor(pts, device="cuda:0"), torch.tensor(tgt, device="cuda:0")
+    with smrt.MLP(max_batch=n) as net:
+        net.set_params(torch.tensor(params * 0.5, dtype=torch.float32, device="cuda:0"),
+                       torch.tensor(B * 0.5, dtype=torch.float32, device="cuda:0"))
+        first = net.train_step(P, T, 2e-3, want_loss=True)
+        for _ in range(400):
+            net.train_step(P, T, 2e-3)
+        last = net.train_step(P, T, 2e-3, want_loss=True)
+    print("training loss %.4e -> %.4e" % (first, last))
+    assert last < first / 20
+
+
+def test_mlp_rejects_bad_shapes(smrt):
+    with smrt.MLP(max_batch=256) as net:
+        with pytest.raises(smrt.SmrtError):
+            net.forward(torch.zeros((64, 3), device="cuda:0"))      # parameters not set
+        net.set_params(torch.zeros(net.param_count, device="cuda:0"),
+                       torch.zeros((16, 3), device="cuda:0"))
+        with pytest.raises(smrt.SmrtError):
+            net.forward(torch.zeros((100, 3), device="cuda:0"))     # not a multiple of 64
+        with pytest.raises(smrt.SmrtError):
+            net.forward(torch.zeros((512, 3), device="cuda:0"))     # above max_batch
