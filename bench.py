@@ -58,11 +58,16 @@ def parse():
     ap.add_argument("--launch", default="", help="bx,by,rows of the stream-collide kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget")
-    ap.add_argument("--workload", default="tg", choices=["tg", "cavity", "precision", "batch"],
+    ap.add_argument("--workload", default="tg",
+                    choices=["tg", "cavity", "precision", "batch", "warmstart"],
                     help="tg: periodic Taylor-Green throughput (default); cavity: lid-driven "
                          "cavity run from the cold start to the steady-state residual; "
                          "precision: one cavity in every storage type against FP64; "
-                         "batch: many cavities of uneven size and Re run together to steady")
+                         "batch: many cavities of uneven size and Re run together to steady; "
+                         "warmstart: learned warm start against the cold start")
+    ap.add_argument("--train", type=int, default=200, help="warmstart: training cavities")
+    ap.add_argument("--held-out", type=int, default=50, help="warmstart: evaluation cavities")
+    ap.add_argument("--epochs", type=int, default=30, help="warmstart: training epochs")
     ap.add_argument("--count", type=int, default=256, help="batch: number of cavities")
     ap.add_argument("--schedule", default="",
                     help="cavity: precision schedule 'f16:1e-5' = run in that storage until the "
@@ -323,6 +328,81 @@ def batch_to_steady(args):
     print(json.dumps(out), flush=True)
 
 
+def warm_start_study(args):
+    """Learned warm start on 256^2 cavities: Re log-uniform in [100, 1e4]
+    (seeded); args.train steady fields from the solver train the network on
+    the GPU; on args.held_out other Re the cold start and the warm start run
+    to the same residual; reports steps, wall time (warm includes inference)
+    and the final-field difference max |du| / U per cavity."""
+    import torch
+    from paper_2409_01076_amd import smrt
+    from paper_2409_01076_amd import warmstart as W
+    n, U = (args.n if args.n != 4096 else 256), 0.1
+    rng = np.random.default_rng(2409010760)
+    re_all = 100.0 * 100.0 ** rng.uniform(0, 1, size=args.train + args.held_out)
+    re_train, re_test = re_all[:args.train], re_all[args.train:]
+    log = lambda msg: print("# " + msg, file=sys.stderr, flush=True)
+
+    def run_batch(res, warm=None):
+        b = smrt.Batch([n] * len(res), [n] * len(res), scheme=args.scheme, storage=args.storage,
+                       re=res, u_lid=U)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if warm is not None:
+            for i, r in enumerate(res):
+                b.init_fields(i, *warm.predict(n, r, U))
+        steps, status, resid = b.run(args.tol, args.window, args.max_steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        fields = [[t.cpu().numpy() for t in b.moments(i)] for i in range(len(res))]
+        b.close()
+        return np.array(steps), np.array(status), fields, wall
+
+    t0 = time.perf_counter()
+    tr_steps, tr_status, tr_fields, tr_wall = run_batch(re_train)
+    log("training data: %d cavities, %d steady, %.1f s" % (len(re_train), (tr_status == smrt.STEADY).sum(), tr_wall))
+    keep = tr_status == smrt.STEADY
+    pts = np.concatenate([W.cavity_points(n, r) for r, k in zip(re_train, keep) if k])
+    tgt = np.concatenate([W.targets(*f, U) for f, k in zip(tr_fields, keep) if k])
+    ws = W.WarmStart(fourier=16, width=128, layers=5, batch=65536)
+    t1 = time.perf_counter()
+    hist = ws.fit(pts, tgt, epochs=args.epochs, lr=2e-3, log=log)
+    train_s = time.perf_counter() - t1
+    cold_steps, cold_status, cold, cold_wall = run_batch(re_test)
+    warm_steps, warm_status, warm, warm_wall = run_batch(re_test, ws)
+    ws.close()
+    per = []
+    for i, r in enumerate(re_test):
+        err = max(np.abs(warm[i][1] - cold[i][1]).max(), np.abs(warm[i][2] - cold[i][2]).max()) / U
+        per.append({"re": round(float(r), 2), "cold_steps": int(cold_steps[i]), "warm_steps": int(warm_steps[i]),
+                    "cold_status": ["cap", "steady", "unstable"][int(cold_status[i])],
+                    "warm_status": ["cap", "steady", "unstable"][int(warm_status[i])],
+                    "final_max_du_over_U": float(err)})
+    both = (cold_status == smrt.STEADY) & (warm_status == smrt.STEADY)
+    out = {
+        "workload": "learned warm start, %dx%d cavities, Re log-uniform [100, 1e4], %d training / %d "
+                    "held-out, U=0.1, %s %s, residual < %g (window %d), cap %d steps"
+                    % (n, n, args.train, args.held_out, args.scheme, args.storage, args.tol, args.window,
+                       args.max_steps),
+        "network": "5 weight layers, width 128, (x, y, log Re) + 16 Fourier features, bf16 MFMA, FP32 accumulation",
+        "training_cavities_steady": int(keep.sum()),
+        "training_data_seconds": round(tr_wall, 2),
+        "training_seconds": round(train_s, 2),
+        "training_loss_first_last": [hist[0][1], hist[-1][1]],
+        "held_out_both_steady": int(both.sum()),
+        "cold_total_steps_both_steady": int(cold_steps[both].sum()),
+        "warm_total_steps_both_steady": int(warm_steps[both].sum()),
+        "median_step_ratio_warm_over_cold": float(np.median(warm_steps[both] / cold_steps[both])) if both.any() else None,
+        "cold_wall_seconds": round(cold_wall, 3),
+        "warm_wall_seconds_including_inference": round(warm_wall, 3),
+        "max_final_field_diff_over_U": float(max(p["final_max_du_over_U"] for p, b in zip(per, both) if b))
+        if both.any() else None,
+        "total_seconds": round(time.perf_counter() - t0, 1),
+        "per_cavity": per,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -346,6 +426,9 @@ def main():
         return
     if args.workload == "batch":
         batch_to_steady(args)
+        return
+    if args.workload == "warmstart":
+        warm_start_study(args)
         return
 
     from paper_2409_01076_amd import inputs, smrt
