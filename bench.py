@@ -362,6 +362,9 @@ def warm_start_study(args):
     tr_steps, tr_status, tr_fields, tr_wall = run_batch(re_train)
     log("training data: %d cavities, %d steady, %.1f s" % (len(re_train), (tr_status == smrt.STEADY).sum(), tr_wall))
     keep = tr_status == smrt.STEADY
+    if not keep.any():
+        raise SystemExit("no training cavity reached the residual %g within %d steps; raise --max-steps"
+                         % (args.tol, args.max_steps))
     pts = np.concatenate([W.cavity_points(n, r) for r, k in zip(re_train, keep) if k])
     tgt = np.concatenate([W.targets(*f, U) for f, k in zip(tr_fields, keep) if k])
     ws = W.WarmStart(fourier=16, width=128, layers=5, batch=65536)

@@ -73,11 +73,14 @@ class WarmStart:
         """points, target: host float32 arrays (N, 3).  Mini-batches of
         `batch` rows from one shuffled order; cosine learning-rate decay.
         Returns the list of (step, loss) recorded once per epoch."""
-        n = (points.shape[0] // self.batch) * self.batch
+        bs = min(self.batch, (points.shape[0] // 64) * 64)
+        if bs == 0:
+            raise ValueError("need at least 64 training rows")
+        n = (points.shape[0] // bs) * bs
         order = np.random.default_rng(seed).permutation(points.shape[0])[:n]
         P = torch.from_numpy(np.ascontiguousarray(points[order])).to(self.device)
         T = torch.from_numpy(np.ascontiguousarray(target[order])).to(self.device)
-        per_epoch = n // self.batch
+        per_epoch = n // bs
         total = epochs * per_epoch
         history = []
         t0 = time.perf_counter()
@@ -86,8 +89,8 @@ class WarmStart:
                 step = e * per_epoch + b
                 rate = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * step / total))
                 last = b == per_epoch - 1
-                loss = self.net.train_step(P[b * self.batch:(b + 1) * self.batch],
-                                           T[b * self.batch:(b + 1) * self.batch], rate, want_loss=last)
+                loss = self.net.train_step(P[b * bs:(b + 1) * bs], T[b * bs:(b + 1) * bs], rate,
+                                           want_loss=last)
             history.append((total if e == epochs - 1 else (e + 1) * per_epoch, loss))
             if log:
                 log("epoch %d loss %.4e (%.1f s)" % (e + 1, loss, time.perf_counter() - t0))
