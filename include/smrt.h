@@ -157,6 +157,21 @@ double smrt_tau(const smrt_ctx* c);
  * SMRT_EINVAL otherwise. */
 int smrt_set_launch(smrt_ctx* c, int32_t bx, int32_t by, int32_t rows);
 
+/* Time steps per kernel launch: 1, or 2 with the LDS-blocked kernel that
+ * keeps the intermediate step on chip, halving the HBM traffic per
+ * node-update (FP32 and 16-bit storage only).  Tile of the two-step kernel:
+ * tile_cols x tile_rows in {64 x 4, 64 x 8, 64 x 16, 128 x 4, 128 x 8}
+ * (0 = 64 x 8); a periodic lattice needs nx >= tile_cols + 2 and
+ * ny >= tile_rows + 2.  Per node the arithmetic is unchanged: results are
+ * bitwise those of single-step launches.  Default at creation: 2 steps with a
+ * 64 x 8 tile (64 x 4 below 4096 tiles) wherever applicable, else 1.  An odd
+ * step count ends with one single-step launch.  SMRT_EINVAL if not
+ * applicable. */
+int smrt_set_steps_per_launch(smrt_ctx* c, int32_t steps, int32_t tile_cols, int32_t tile_rows);
+
+/* Time steps per launch in use (1 or 2); -1 for c == NULL. */
+int32_t smrt_get_steps_per_launch(const smrt_ctx* c);
+
 /* Waits for all work enqueued on the context's stream. */
 int smrt_synchronize(smrt_ctx* c);
 

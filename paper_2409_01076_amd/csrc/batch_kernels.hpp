@@ -24,7 +24,7 @@ struct CavityDesc {
 };
 
 struct BatchLaunch {
-    int bx, by;
+    int bx, by; // tile (and, for one-step launches, block) shape
 };
 
 // Descriptor tables are read-only during a launch and the same for a whole
@@ -94,6 +94,42 @@ __global__ void __launch_bounds__(1024) batch_stream_collide(const CavityDesc* _
         const Coef<C> k = coef_of<C>(c);
         collide<SCHEME, T>(d, k);
         scatter_store<T>(dst, g, x, y, d);
+    }
+}
+
+// Two time steps of every listed tile per launch: the batch form of
+// stream_collide_x2 (same two phases through LDS), for tiles of TX x TY
+// nodes and X2_THREADS threads.  Cavity walls need no wrap, so any size works.
+template <typename T, int SCHEME, int TX, int TY>
+__global__ void __launch_bounds__(X2_THREADS) batch_stream_collide_x2(const CavityDesc* __restrict__ cav,
+                                                                     const int2* __restrict__ tiles,
+                                                                     const int* __restrict__ ntiles_p,
+                                                                     T* __restrict__ base, int parity)
+{
+    using C = typename Storage<T>::C;
+    __shared__ X2Tile<T, TX, TY> sh;
+    const int ntiles = *ntiles_p;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int2 tt = tiles[t];
+        const CavityDesc c = load_desc(cav, __builtin_amdgcn_readfirstlane(tt.x));
+        const int ti = __builtin_amdgcn_readfirstlane(tt.y);
+        Geom g;
+        g.nx = c.nx;
+        g.ny = c.ny;
+        g.pitch = c.pitch;
+        g.plane = c.plane;
+        g.bx = TX;
+        g.by = TY;
+        g.rows = 1;
+        g.tiles_x = c.tiles_x;
+        const T* src = base + (parity ? c.off[1] : c.off[0]);
+        T* dst = base + (parity ? c.off[0] : c.off[1]);
+        const Coef<C> k = coef_of<C>(c);
+        const int X0 = (ti % c.tiles_x) * TX, Y0 = (ti / c.tiles_x) * TY;
+        x2_phase1<T, SCHEME, CAVITY, TX, TY>(src, g, k, X0, Y0, sh);
+        __syncthreads();
+        x2_phase2<T, SCHEME, CAVITY, TX, TY>(dst, g, k, X0, Y0, sh);
+        __syncthreads(); // the next tile reuses the LDS
     }
 }
 

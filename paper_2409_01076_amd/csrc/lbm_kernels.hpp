@@ -333,6 +333,111 @@ __global__ void __launch_bounds__(1024) stream_collide(const T* __restrict__ src
     }
 }
 
+// Two time steps per launch (temporal blocking).  A workgroup owns a
+// TX x TY tile of outputs.  Phase 1 computes step t+1 (gather from the
+// previous buffer, collide) on the tile plus a one-node ring and keeps it in
+// LDS; phase 2 pulls from LDS, collides again and stores step t+2.  The HBM
+// traffic per node-update halves (read d(t), write d(t+2)); the ring adds
+// (TX + 2)(TY + 2) / (TX TY) - 1 redundant collisions.  Per node the
+// arithmetic is that of stream_collide (same gather, collide and, for 16-bit
+// storage, the same rounding to the storage grid between the steps), so the
+// results are bitwise those of two one-step launches.
+constexpr int X2_THREADS = 256;
+
+template <typename T, int TX, int TY> struct X2Tile {
+    using C = typename Storage<T>::C;
+    static constexpr int RX = TX + 2, RY = TY + 2;
+    static constexpr int P1 = (RX * RY + X2_THREADS - 1) / X2_THREADS; // ring nodes per thread
+    static constexpr int P2 = (TX * TY + X2_THREADS - 1) / X2_THREADS; // tile nodes per thread
+    C mid[9][RY][RX];                                                  // step t+1 (LDS)
+};
+
+// Phase 1.  Each thread first issues the loads of all its ring nodes, then
+// collides them, so up to 9 P1 loads per lane are in flight together.  A
+// periodic ring wraps once (nx >= TX + 2, ny >= TY + 2); a cavity ring
+// skips the nodes beyond the walls.
+template <typename T, int SCHEME, int BC, int TX, int TY>
+__device__ __forceinline__ void x2_phase1(const T* __restrict__ src, const Geom& g,
+                                          const Coef<typename Storage<T>::C>& k, int X0, int Y0,
+                                          X2Tile<T, TX, TY>& sh)
+{
+    using Tl = X2Tile<T, TX, TY>;
+    using C = typename Storage<T>::C;
+    C d[Tl::P1][9];
+    bool live[Tl::P1];
+#pragma unroll
+    for (int j = 0; j < Tl::P1; ++j) {
+        const int i = threadIdx.x + j * X2_THREADS;
+        const int lx = i % Tl::RX, ly = i / Tl::RX;
+        int x = X0 - 1 + lx, y = Y0 - 1 + ly;
+        if constexpr (BC == PERIODIC) {
+            x = x < 0 ? x + g.nx : (x >= g.nx ? x - g.nx : x);
+            y = y < 0 ? y + g.ny : (y >= g.ny ? y - g.ny : y);
+            live[j] = i < Tl::RX * Tl::RY;
+        } else {
+            live[j] = i < Tl::RX * Tl::RY && (unsigned)x < (unsigned)g.nx && (unsigned)y < (unsigned)g.ny;
+        }
+        if (live[j]) {
+            const bool edge = (x == 0) | (x == g.nx - 1) | (y == 0) | (y == g.ny - 1);
+            if (edge)
+                gather_edge<T, BC>(src, g, x, y, d[j], k.lid);
+            else
+                gather_interior<T>(src, g, x, y, d[j]);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < Tl::P1; ++j) {
+        if (!live[j]) continue;
+        const int i = threadIdx.x + j * X2_THREADS;
+        const int lx = i % Tl::RX, ly = i / Tl::RX;
+        collide<SCHEME, T>(d[j], k);
+        if constexpr (Storage<T>::kRounds) d[j][0] = Storage<T>::stored_value(d[j][0], 0);
+#pragma unroll
+        for (int a = 0; a < 9; ++a) sh.mid[a][ly][lx] = d[j][a];
+    }
+}
+
+// Phase 2: pull step t+1 from LDS (bounce-back from the node's own opposite
+// population where the source lies beyond a cavity wall), collide, store t+2.
+template <typename T, int SCHEME, int BC, int TX, int TY>
+__device__ __forceinline__ void x2_phase2(T* __restrict__ dst, const Geom& g, const Coef<typename Storage<T>::C>& k,
+                                          int X0, int Y0, const X2Tile<T, TX, TY>& sh)
+{
+    using C = typename Storage<T>::C;
+    for (int i = threadIdx.x; i < TX * TY; i += X2_THREADS) {
+        const int tx = i % TX, ty = i / TX;
+        const int x = X0 + tx, y = Y0 + ty;
+        if (x >= g.nx || y >= g.ny) continue;
+        const int lx = tx + 1, ly = ty + 1;
+        C d[9];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            const C pulled = sh.mid[a][ly - EY[a]][lx - EX[a]];
+            if constexpr (BC == CAVITY) {
+                const int sx = x - EX[a], sy = y - EY[a];
+                const bool inside = (unsigned)sx < (unsigned)g.nx && (unsigned)sy < (unsigned)g.ny;
+                const C own = sh.mid[OPP[a]][ly][lx];
+                d[a] = inside ? pulled : ((sy == g.ny) ? own + C(EX[a]) * k.lid : own);
+            } else {
+                d[a] = pulled;
+            }
+        }
+        collide<SCHEME, T>(d, k);
+        scatter_store<T>(dst, g, x, y, d);
+    }
+}
+
+template <typename T, int SCHEME, int BC, int TX, int TY>
+__global__ void __launch_bounds__(X2_THREADS) stream_collide_x2(const T* __restrict__ src, T* __restrict__ dst,
+                                                               Geom g, Coef<typename Storage<T>::C> k)
+{
+    __shared__ X2Tile<T, TX, TY> sh;
+    const int X0 = (blockIdx.x % g.tiles_x) * TX, Y0 = (blockIdx.x / g.tiles_x) * TY;
+    x2_phase1<T, SCHEME, BC, TX, TY>(src, g, k, X0, Y0, sh);
+    __syncthreads();
+    x2_phase2<T, SCHEME, BC, TX, TY>(dst, g, k, X0, Y0, sh);
+}
+
 // ---------------------------------------------------------------------------
 // Initialisation, export and reductions (off the per-step path).
 

@@ -197,6 +197,8 @@ struct smrt_ctx {
     int cur = 0;                   // 0: state in buffer A, 1: in buffer B
     int64_t steps = 0, snap_step = 0;
     int bx = 256, by = 1, rows = 1;
+    int fused = 1;                 // time steps per launch (1, or 2 with the LDS-blocked kernel)
+    int fused_cols = 64, fused_rows = 8; // tile of the two-step kernel
 
     void* buffer(int which) const { return ws + (which == 0 ? L.off_a : L.off_b); }
     double* snap_x() const { return reinterpret_cast<double*>(ws + L.off_snap_x); }
@@ -258,6 +260,66 @@ template <typename T> int launch_step(smrt_ctx* c, const void* src, void* dst)
         break;
     }
     return SMRT_OK;
+}
+
+template <typename T, int TX, int TY> int launch_step2_tile(smrt_ctx* c, const void* src, void* dst)
+{
+    using C = typename smrt::Storage<T>::C;
+    smrt::Geom g = c->geom();
+    g.tiles_x = (g.nx + TX - 1) / TX;
+    const int tiles_y = (g.ny + TY - 1) / TY;
+    smrt::Coef<C> k;
+    const double omega = 1.0 / c->tau;
+    const double omega_s = c->p.scheme == SMRT_SCHEME_TRT ? 1.0 / c->p.tau_s : 1.0;
+    k.omega = (C)omega;
+    k.omega_s = (C)omega_s;
+    k.a = (C)(1.0 - omega);
+    k.b = (C)(omega_s - omega);
+    k.lid = (C)(c->p.boundary == SMRT_CAVITY ? c->p.u_lid / 6.0 : 0.0);
+    const int64_t blocks = (int64_t)g.tiles_x * tiles_y;
+    if (blocks > std::numeric_limits<int>::max()) return fail(SMRT_EINVAL, "grid too large");
+    const T* s = static_cast<const T*>(src);
+    T* d = static_cast<T*>(dst);
+    const dim3 grid((unsigned)blocks), block(smrt::X2_THREADS);
+    const bool per = c->p.boundary == SMRT_PERIODIC;
+    switch (c->p.scheme) {
+    case SMRT_SCHEME_SRT:
+        if (per) smrt::stream_collide_x2<T, smrt::SRT, smrt::PERIODIC, TX, TY><<<grid, block, 0, c->stream>>>(s, d, g, k);
+        else smrt::stream_collide_x2<T, smrt::SRT, smrt::CAVITY, TX, TY><<<grid, block, 0, c->stream>>>(s, d, g, k);
+        break;
+    case SMRT_SCHEME_SMRT:
+        if (per) smrt::stream_collide_x2<T, smrt::SMRT, smrt::PERIODIC, TX, TY><<<grid, block, 0, c->stream>>>(s, d, g, k);
+        else smrt::stream_collide_x2<T, smrt::SMRT, smrt::CAVITY, TX, TY><<<grid, block, 0, c->stream>>>(s, d, g, k);
+        break;
+    default:
+        if (per) smrt::stream_collide_x2<T, smrt::TRT, smrt::PERIODIC, TX, TY><<<grid, block, 0, c->stream>>>(s, d, g, k);
+        else smrt::stream_collide_x2<T, smrt::TRT, smrt::CAVITY, TX, TY><<<grid, block, 0, c->stream>>>(s, d, g, k);
+        break;
+    }
+    return SMRT_OK;
+}
+
+// Two-step tiles offered: 64 x {4, 8, 16} and 128 x {4, 8}.
+template <typename T> int launch_step2(smrt_ctx* c, const void* src, void* dst)
+{
+    if (c->fused_cols == 128) {
+        if (c->fused_rows == 4) return launch_step2_tile<T, 128, 4>(c, src, dst);
+        return launch_step2_tile<T, 128, 8>(c, src, dst);
+    }
+    if (c->fused_rows == 4) return launch_step2_tile<T, 64, 4>(c, src, dst);
+    if (c->fused_rows == 16) return launch_step2_tile<T, 64, 16>(c, src, dst);
+    return launch_step2_tile<T, 64, 8>(c, src, dst);
+}
+
+// Two time steps in one launch (FP32 and 16-bit storage only).
+int dispatch_step2(smrt_ctx* c, const void* src, void* dst)
+{
+    switch (c->p.storage) {
+    case SMRT_F32: return launch_step2<float>(c, src, dst);
+    case SMRT_F16: return launch_step2<_Float16>(c, src, dst);
+    case SMRT_BF16: return launch_step2<smrt::bf16>(c, src, dst);
+    default: return fail(SMRT_EINVAL, "two-step launches need FP32 or 16-bit storage");
+    }
 }
 
 int dispatch_step(smrt_ctx* c, const void* src, void* dst)
@@ -363,6 +425,16 @@ int smrt_create(const smrt_params* p, void* dev_ws, size_t ws_bytes, smrt_ctx** 
         c->L = L;
         // Default block shape: one row segment per block, as wide as the
         // lattice allows (512 measured best on 4096^2, within 1-2% of 256).
+        // Two steps per launch wherever the LDS-blocked kernel applies (FP32
+        // and 16-bit storage; periodic lattices at least a tile plus its
+        // ring): 64 x 8 tiles when that still gives >= 4096 workgroups, else
+        // 64 x 4 (measured best on 256^2 .. 4096^2).
+        if (p->storage != SMRT_F64) {
+            const int64_t tiles8 = (int64_t)((p->nx + 63) / 64) * ((p->ny + 7) / 8);
+            c->fused_cols = 64;
+            c->fused_rows = tiles8 >= 4096 ? 8 : 4;
+            if (p->boundary == SMRT_CAVITY || (p->nx >= 66 && p->ny >= c->fused_rows + 2)) c->fused = 2;
+        }
         if (p->nx >= 512) {
             c->bx = 512; c->by = 1;
         } else if (p->nx >= 256) {
@@ -452,11 +524,15 @@ int smrt_step(smrt_ctx* c, int64_t n)
 {
     if (!c) return fail(SMRT_EINVAL, "context is NULL");
     if (n < 0) return fail(SMRT_EINVAL, "step count must be >= 0 (got %lld)", (long long)n);
-    for (int64_t i = 0; i < n; ++i) {
-        int rc = dispatch_step(c, c->buffer(c->cur), c->buffer(c->cur ^ 1));
+    int64_t left = n;
+    while (left > 0) {
+        const bool two = c->fused == 2 && left >= 2;
+        int rc = two ? dispatch_step2(c, c->buffer(c->cur), c->buffer(c->cur ^ 1))
+                     : dispatch_step(c, c->buffer(c->cur), c->buffer(c->cur ^ 1));
         if (rc) return rc;
         c->cur ^= 1;
-        c->steps += 1;
+        c->steps += two ? 2 : 1;
+        left -= two ? 2 : 1;
     }
     return n ? after_launch("stream_collide") : SMRT_OK;
 }
@@ -531,6 +607,30 @@ int smrt_set_launch(smrt_ctx* c, int32_t bx, int32_t by, int32_t rows)
     c->rows = rows;
     return SMRT_OK;
 }
+
+int smrt_set_steps_per_launch(smrt_ctx* c, int32_t steps, int32_t tile_cols, int32_t tile_rows)
+{
+    if (!c) return fail(SMRT_EINVAL, "context is NULL");
+    if (steps != 1 && steps != 2) return fail(SMRT_EINVAL, "steps per launch must be 1 or 2 (got %d)", steps);
+    if (tile_cols == 0) tile_cols = 64;
+    if (tile_rows == 0) tile_rows = 8;
+    const bool ok = (tile_cols == 64 && (tile_rows == 4 || tile_rows == 8 || tile_rows == 16)) ||
+                    (tile_cols == 128 && (tile_rows == 4 || tile_rows == 8));
+    if (!ok) return fail(SMRT_EINVAL, "two-step tile %d x %d not offered", tile_cols, tile_rows);
+    if (steps == 2) {
+        if (c->p.storage == SMRT_F64) return fail(SMRT_EINVAL, "two-step launches need FP32 or 16-bit storage");
+        // A periodic ring wraps once, which needs the lattice wider than the tile.
+        if (c->p.boundary == SMRT_PERIODIC && (c->p.nx < tile_cols + 2 || c->p.ny < tile_rows + 2))
+            return fail(SMRT_EINVAL, "periodic two-step launches need nx >= %d and ny >= %d", tile_cols + 2,
+                        tile_rows + 2);
+    }
+    c->fused = steps;
+    c->fused_cols = tile_cols;
+    c->fused_rows = tile_rows;
+    return SMRT_OK;
+}
+
+int32_t smrt_get_steps_per_launch(const smrt_ctx* c) { return c ? c->fused : -1; }
 
 int smrt_synchronize(smrt_ctx* c)
 {

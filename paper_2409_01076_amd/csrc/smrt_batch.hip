@@ -154,6 +154,7 @@ struct smrt_batch {
     bool owns_ws = false;
     double* host_result = nullptr;  // pinned, count * RED_VALUES
     smrt::BatchLaunch shape{64, 4};
+    bool two = false;               // two time steps per launch (LDS-blocked kernel)
     int grid = 0;                   // workgroups per step launch
     int parity = 0;                 // buffer holding the running cavities' state
     int64_t steps = 0, snap_step = 0;
@@ -217,43 +218,53 @@ int upload_tables(smrt_batch* b)
     return SMRT_OK;
 }
 
-template <typename T>
-void launch_step_typed(smrt_batch* b, hipStream_t s, int parity)
+template <typename T, int SCHEME, int TY>
+void launch_two_tile(smrt_batch* b, hipStream_t s, int parity, dim3 grid)
 {
-    dim3 grid((unsigned)std::max(b->grid, 1)), block(b->shape.bx, b->shape.by);
-    T* base = reinterpret_cast<T*>(b->state());
+    smrt::batch_stream_collide_x2<T, SCHEME, 64, TY><<<grid, smrt::X2_THREADS, 0, s>>>(
+        b->desc(), b->table(), b->ntiles_dev(), reinterpret_cast<T*>(b->state()), parity);
+}
+
+template <typename T, int SCHEME> void launch_typed_scheme(smrt_batch* b, hipStream_t s, int parity, bool two)
+{
+    dim3 grid((unsigned)std::max(b->grid, 1));
+    if (two) {
+        if (b->shape.by == 8) launch_two_tile<T, SCHEME, 8>(b, s, parity, grid);
+        else launch_two_tile<T, SCHEME, 4>(b, s, parity, grid);
+        return;
+    }
+    dim3 block(b->shape.bx, b->shape.by);
+    smrt::batch_stream_collide<T, SCHEME><<<grid, block, 0, s>>>(b->desc(), b->table(), b->ntiles_dev(),
+                                                                reinterpret_cast<T*>(b->state()), parity, b->shape);
+}
+
+template <typename T> void launch_step_typed(smrt_batch* b, hipStream_t s, int parity, bool two)
+{
     switch (b->p.scheme) {
-    case SMRT_SCHEME_SRT:
-        smrt::batch_stream_collide<T, smrt::SRT><<<grid, block, 0, s>>>(b->desc(), b->table(), b->ntiles_dev(), base,
-                                                                      parity, b->shape);
-        break;
-    case SMRT_SCHEME_SMRT:
-        smrt::batch_stream_collide<T, smrt::SMRT><<<grid, block, 0, s>>>(b->desc(), b->table(), b->ntiles_dev(), base,
-                                                                       parity, b->shape);
-        break;
-    default:
-        smrt::batch_stream_collide<T, smrt::TRT><<<grid, block, 0, s>>>(b->desc(), b->table(), b->ntiles_dev(), base,
-                                                                      parity, b->shape);
-        break;
+    case SMRT_SCHEME_SRT: launch_typed_scheme<T, smrt::SRT>(b, s, parity, two); break;
+    case SMRT_SCHEME_SMRT: launch_typed_scheme<T, smrt::SMRT>(b, s, parity, two); break;
+    default: launch_typed_scheme<T, smrt::TRT>(b, s, parity, two); break;
     }
 }
 
-void launch_step(smrt_batch* b, hipStream_t s, int parity)
+// One launch: one time step, or two when `two` (FP64 storage has no
+// two-step kernel).
+void launch_step(smrt_batch* b, hipStream_t s, int parity, bool two)
 {
     switch (b->p.storage) {
-    case SMRT_F64: launch_step_typed<double>(b, s, parity); break;
-    case SMRT_F32: launch_step_typed<float>(b, s, parity); break;
-    case SMRT_F16: launch_step_typed<_Float16>(b, s, parity); break;
-    default: launch_step_typed<smrt::bf16>(b, s, parity); break;
+    case SMRT_F64: launch_step_typed<double>(b, s, parity, false); break;
+    case SMRT_F32: launch_step_typed<float>(b, s, parity, two); break;
+    case SMRT_F16: launch_step_typed<_Float16>(b, s, parity, two); break;
+    default: launch_step_typed<smrt::bf16>(b, s, parity, two); break;
     }
 }
 
-// Captures kGraphSteps step launches starting from `parity` on the private
-// stream and instantiates them.
+// Captures kGraphSteps launches (of one or two steps each, by the current
+// mode) starting from `parity` on the private stream and instantiates them.
 int capture_graph(smrt_batch* b, int parity)
 {
     HIP_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < kGraphSteps; ++i) launch_step(b, b->capture, parity ^ (i & 1));
+    for (int i = 0; i < kGraphSteps; ++i) launch_step(b, b->capture, parity ^ (i & 1), b->two);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(b->capture, &g);
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
@@ -268,25 +279,30 @@ int capture_graph(smrt_batch* b, int parity)
     return SMRT_OK;
 }
 
+bool two_step_mode(const smrt_batch* b) { return b->two && b->p.storage != SMRT_F64; }
+
 int enqueue_steps(smrt_batch* b, int64_t n)
 {
     if (b->ntiles == 0 || n <= 0) return SMRT_OK;
+    const int unit = two_step_mode(b) ? 2 : 1;
+    const int64_t per_graph = (int64_t)kGraphSteps * unit;
     while (n > 0) {
-        if (n >= kGraphSteps) {
+        if (n >= per_graph) {
             if (!b->exec[b->parity]) {
                 int rc = capture_graph(b, b->parity);
                 if (rc) return rc;
             }
             HIP_TRY(hipGraphLaunch(b->exec[b->parity], b->stream));
-            n -= kGraphSteps;
-            b->steps += kGraphSteps;
+            n -= per_graph;
+            b->steps += per_graph;
         } else {
-            launch_step(b, b->stream, b->parity);
+            const bool two = unit == 2 && n >= 2;
+            launch_step(b, b->stream, b->parity, two);
             int rc = after_launch("batch_stream_collide");
             if (rc) return rc;
             b->parity ^= 1;
-            n -= 1;
-            b->steps += 1;
+            n -= two ? 2 : 1;
+            b->steps += two ? 2 : 1;
         }
     }
     return SMRT_OK;
@@ -417,8 +433,10 @@ int smrt_batch_create(const smrt_batch_params* p, void* dev_ws, size_t ws_bytes,
             smrt_batch_destroy(b);
             return hip_fail(e, "hipMemsetAsync");
         }
-        // Default launch: 64 x 4 tiles, one pass over the table per step.
+        // Default launch: 64 x 4 tiles, one pass over the table per launch,
+        // two time steps per launch except for FP64 storage.
         b->shape = kShapes[0];
+        b->two = p->storage != SMRT_F64;
         int total_tiles = 0;
         for (const auto& c : b->plan.desc) total_tiles += tiles_of(c.nx, c.ny, b->shape);
         b->grid = total_tiles;
@@ -516,32 +534,42 @@ int smrt_batch_autotune(smrt_batch* b, int32_t steps, int32_t* chosen)
     float best = std::numeric_limits<float>::infinity();
     smrt::BatchLaunch best_shape = b->shape;
     int best_grid = b->grid;
+    bool best_two = b->two;
     int rc = SMRT_OK;
-    for (int s = 0; s < kNumShapes && rc == SMRT_OK; ++s) {
-        b->shape = kShapes[s];
+    // Candidates: every one-step shape, then (except for FP64) the two-step
+    // kernel with 64 x 4 and 64 x 8 tiles; times are per time step.
+    const int n_two = b->p.storage == SMRT_F64 ? 0 : 2;
+    for (int s = 0; s < kNumShapes + n_two && rc == SMRT_OK; ++s) {
+        const bool two = s >= kNumShapes;
+        b->shape = two ? smrt::BatchLaunch{64, s == kNumShapes ? 4 : 8} : kShapes[s];
+        b->two = two;
         rc = upload_tables(b);
         if (rc) break;
-        const int per_block_waves = (b->shape.bx * b->shape.by) / 64;
+        const int per_block_waves = two ? smrt::X2_THREADS / 64 : (b->shape.bx * b->shape.by) / 64;
         const int grids[] = {b->ntiles, cus * std::max(1, 8 / per_block_waves), cus * std::max(1, 16 / per_block_waves),
                              cus * std::max(1, 32 / per_block_waves)};
         for (int gi = 0; gi < 4; ++gi) {
             b->grid = std::min(grids[gi], b->ntiles);
             if (gi > 0 && grids[gi] >= b->ntiles) continue; // same as the full grid
-            launch_step(b, b->stream, b->parity); // warm-up pair
-            launch_step(b, b->stream, b->parity ^ 1);
+            const int unit = two ? 2 : 1;
+            const int launches = std::max(2, steps / unit) & ~1; // even: parity kept
+            launch_step(b, b->stream, b->parity, two); // warm-up pair
+            launch_step(b, b->stream, b->parity ^ 1, two);
             HIP_TRY(hipEventRecord(e0, b->stream));
-            for (int k = 0; k < steps; ++k) launch_step(b, b->stream, b->parity ^ (k & 1));
+            for (int k = 0; k < launches; ++k) launch_step(b, b->stream, b->parity ^ (k & 1), two);
             HIP_TRY(hipEventRecord(e1, b->stream));
             rc = after_launch("batch autotune");
             if (rc) break;
             HIP_TRY(hipEventSynchronize(e1));
-            b->steps += steps + 2;
+            b->steps += (int64_t)(launches + 2) * unit;
             float ms = 0.0f;
             HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best) {
-                best = ms;
+            const float per_step = ms / (float)(launches * unit);
+            if (per_step < best) {
+                best = per_step;
                 best_shape = b->shape;
                 best_grid = b->grid;
+                best_two = two;
             }
         }
     }
@@ -549,6 +577,7 @@ int smrt_batch_autotune(smrt_batch* b, int32_t steps, int32_t* chosen)
     (void)hipEventDestroy(e1);
     if (rc) return rc;
     b->shape = best_shape;
+    b->two = best_two;
     rc = upload_tables(b);
     if (rc) return rc;
     b->grid = std::min(best_grid, b->ntiles);

@@ -22,7 +22,9 @@ _IO_DTYPES = {torch.float64: 0, torch.float32: 1}
 EXPORTED = (
     "smrt_workspace_bytes", "smrt_create", "smrt_init_fields", "smrt_set_populations",
     "smrt_get_populations", "smrt_step", "smrt_moments", "smrt_residual", "smrt_mass",
-    "smrt_steps_done", "smrt_tau", "smrt_set_launch", "smrt_synchronize", "smrt_destroy",
+    "smrt_steps_done", "smrt_tau", "smrt_set_launch", "smrt_set_steps_per_launch",
+    "smrt_get_steps_per_launch",
+    "smrt_synchronize", "smrt_destroy",
     "smrt_last_error", "smrt_copy_kernel",
     "smrt_batch_workspace_bytes", "smrt_batch_create", "smrt_batch_step", "smrt_batch_run",
     "smrt_batch_autotune", "smrt_batch_moments", "smrt_batch_init_fields", "smrt_batch_steps_done",
@@ -105,6 +107,8 @@ def load():
         "smrt_steps_done": (i64, [vp]),
         "smrt_tau": (ctypes.c_double, [vp]),
         "smrt_set_launch": (ctypes.c_int, [vp, i32, i32, i32]),
+        "smrt_set_steps_per_launch": (ctypes.c_int, [vp, i32, i32, i32]),
+        "smrt_get_steps_per_launch": (i32, [vp]),
         "smrt_synchronize": (ctypes.c_int, [vp]),
         "smrt_destroy": (None, [vp]),
         "smrt_last_error": (ctypes.c_char_p, []),
@@ -229,6 +233,10 @@ class Solver:
     def steps_done(self):
         return int(load().smrt_steps_done(self._ctx))
 
+    @property
+    def steps_per_launch(self):
+        return int(load().smrt_get_steps_per_launch(self._ctx))
+
     def _io(self, t, shape):
         if t is None:
             return None
@@ -325,6 +333,11 @@ class Solver:
 
     def set_launch(self, bx, by, rows=1):
         _check(load().smrt_set_launch(self._ctx, int(bx), int(by), int(rows)))
+
+    def set_steps_per_launch(self, steps, tile_rows=0, tile_cols=0):
+        """1, or 2 for the two-step LDS-blocked kernel (FP32/16-bit storage);
+        tile 64 x {4, 8, 16} or 128 x {4, 8} (0 = default 64 x 8)."""
+        _check(load().smrt_set_steps_per_launch(self._ctx, int(steps), int(tile_cols), int(tile_rows)))
 
     def synchronize(self):
         _check(load().smrt_synchronize(self._ctx))

@@ -188,9 +188,11 @@ def test_bitwise_deterministic_across_runs_and_launch_shapes(smrt):
     n = 200
     rho, ux, uy = inputs.taylor_green(n, n + 3, u0=0.05, seed=3)
     outs = []
-    for shape in ((64, 4, 1), (64, 4, 1), (128, 2, 3), (256, 1, 2), (16, 16, 1)):
+    for shape in ((64, 4, 1), (64, 4, 1), (128, 2, 3), (256, 1, 2), (16, 16, 1), None):
         with smrt.Solver(n, n + 3, scheme="smrt", boundary="periodic", storage="f32", tau=0.55) as s:
-            s.set_launch(*shape)
+            if shape is not None:
+                s.set_steps_per_launch(1)
+                s.set_launch(*shape)            # else the default two-step launches
             s.init_fields(to_dev(rho), to_dev(ux), to_dev(uy))
             s.step(50)
             outs.append(s.populations(torch.float32).cpu().numpy())
@@ -342,3 +344,64 @@ def test_convert_between_storage_types(smrt):
         assert float((fa - fb).abs().max()) == 0.0   # FP16 values are exact in FP32
         b.step(10)
         assert np.isfinite(b.residual())
+
+
+# --- two time steps per launch (LDS-blocked kernel) ----------------------------------------
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("boundary", ["periodic", "cavity"])
+@pytest.mark.parametrize("scheme", ["srt", "smrt", "trt"])
+@pytest.mark.parametrize("tile", [(64, 4), (64, 8), (64, 16), (128, 4), (128, 8)])
+def test_two_step_kernel_equals_single_steps(smrt, storage, boundary, scheme, tile):
+    """The same per-node arithmetic: bitwise equal to one-step launches, on a
+    ragged lattice (tiles cut at both edges) over an odd step count."""
+    nx, ny, steps = 203, 77, 41      # 203 = 3 x 64 + 11 = 128 + 75: ragged for both tile widths
+    f0 = inputs.perturbed_populations(nx, ny, eps=0.03, seed=5)
+    u = 0.1 if boundary == "cavity" else 0.0
+    outs = []
+    for spl in (1, 2):
+        with smrt.Solver(nx, ny, scheme=scheme, boundary=boundary, storage=storage, tau=0.56,
+                         u_lid=u, tau_s=0.9) as s:
+            s.set_populations(to_dev(f0, torch.float64))
+            s.set_steps_per_launch(spl, tile_rows=tile[1], tile_cols=tile[0])
+            s.step(steps)
+            assert s.steps_done == steps
+            outs.append(s.populations(torch.float64).cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("nx,ny", [(3, 3), (5, 70), (64, 64), (65, 9)])
+def test_two_step_kernel_small_cavities(smrt, nx, ny):
+    """Cavities need no wrap, so any size takes two-step launches."""
+    outs = []
+    for spl in (1, 2):
+        with smrt.Solver(nx, ny, scheme="smrt", boundary="cavity", storage="f32", tau=0.6,
+                         u_lid=0.1) as s:
+            s.set_steps_per_launch(spl, tile_rows=4)
+            s.step(30)
+            outs.append(s.populations(torch.float64).cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_two_step_kernel_against_oracle(smrt):
+    n, u, steps = 96, 0.1, 600
+    with smrt.Solver(n, n, scheme="smrt", boundary="cavity", storage="f32", re=300.0, u_lid=u) as s:
+        s.set_steps_per_launch(2)
+        s.step(steps)
+        g = gpu_fields(s)
+    L = O.Lattice(n, n, "smrt", re=300.0, u_lid=u)
+    o = L.fields(L.run(L.init_equilibrium(), steps))
+    assert max_vel_err(g, o) / u <= TOL["f32"]
+
+
+def test_two_step_kernel_rejects_unsupported(smrt):
+    with smrt.Solver(64, 64, scheme="smrt", boundary="periodic", storage="f32", tau=0.7) as s:
+        with pytest.raises(smrt.SmrtError):
+            s.set_steps_per_launch(2)          # periodic, nx < 66
+        with pytest.raises(smrt.SmrtError):
+            s.set_steps_per_launch(2, tile_rows=16, tile_cols=128)   # tile not offered
+    with smrt.Solver(128, 128, scheme="smrt", boundary="cavity", storage="f64", tau=0.7, u_lid=0.1) as s:
+        with pytest.raises(smrt.SmrtError):
+            s.set_steps_per_launch(2)          # FP64 storage
+        with pytest.raises(smrt.SmrtError):
+            s.set_steps_per_launch(3)
