@@ -172,6 +172,16 @@ int smrt_set_steps_per_launch(smrt_ctx* c, int32_t steps, int32_t tile_cols, int
 /* Time steps per launch in use (1 or 2); -1 for c == NULL. */
 int32_t smrt_get_steps_per_launch(const smrt_ctx* c);
 
+/* Order in which the two-step kernel's workgroups take their tiles (a
+ * performance knob only: every order computes bitwise the same result).
+ * panel_cols = 0: row-major.  panel_cols = P > 0: the tile columns are cut
+ * into panels of P, each walked top to bottom, and each of the GPU's 8 XCDs
+ * takes one contiguous run of that order, so neighbouring tiles share an L2
+ * and the halo rows and columns they both read are fetched from memory once.
+ * Default at creation: 8 for FP32 storage, 0 otherwise.  SMRT_EINVAL for
+ * c == NULL or panel_cols < 0. */
+int smrt_set_tile_order(smrt_ctx* c, int32_t panel_cols);
+
 /* Waits for all work enqueued on the context's stream. */
 int smrt_synchronize(smrt_ctx* c);
 

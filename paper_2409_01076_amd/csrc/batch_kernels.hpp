@@ -77,23 +77,27 @@ __global__ void __launch_bounds__(1024) batch_stream_collide(const CavityDesc* _
         g.by = L.by;
         g.rows = 1;
         g.tiles_x = c.tiles_x;
+        g.panel = 0;
         const int ti = __builtin_amdgcn_readfirstlane(tt.y);
+        const int ytile = (ti / c.tiles_x) * L.by;
         const int x = (ti % c.tiles_x) * L.bx + threadIdx.x;
-        const int y = (ti / c.tiles_x) * L.by + threadIdx.y;
-        if (x >= c.nx || y >= c.ny) continue;
+        const int y = ytile + threadIdx.y;
         // select, not c.off[parity]: a runtime index into the local copy of
         // the descriptor would put it in scratch memory
         const T* src = base + (parity ? c.off[1] : c.off[0]);
         T* dst = base + (parity ? c.off[0] : c.off[1]);
+        const PullBases<T> pb = pull_bases(src, g, ytile > 0 ? ytile - 1 : 0);
+        const StoreBases<T> sb = store_bases(dst, g, ytile);
+        if (x >= c.nx || y >= c.ny) continue;
         C d[9];
         const bool edge = (x == 0) | (x == c.nx - 1) | (y == 0) | (y == c.ny - 1);
         if (edge)
             gather_edge<T, CAVITY>(src, g, x, y, d, (C)c.lid);
         else
-            gather_interior<T>(src, g, x, y, d);
+            gather_interior<T>(pb, g, x, y, d);
         const Coef<C> k = coef_of<C>(c);
         collide<SCHEME, T>(d, k);
-        scatter_store<T>(dst, g, x, y, d);
+        scatter_store<T>(sb, g, x, y, d);
     }
 }
 
@@ -122,6 +126,7 @@ __global__ void __launch_bounds__(X2_THREADS) batch_stream_collide_x2(const Cavi
         g.by = TY;
         g.rows = 1;
         g.tiles_x = c.tiles_x;
+        g.panel = 0;
         const T* src = base + (parity ? c.off[1] : c.off[0]);
         T* dst = base + (parity ? c.off[0] : c.off[1]);
         const Coef<C> k = coef_of<C>(c);

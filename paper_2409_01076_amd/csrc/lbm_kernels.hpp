@@ -134,7 +134,40 @@ struct Geom {
     int64_t plane; // elements per direction plane
     int bx, by, rows;
     int tiles_x;   // tiles along x
+    int panel;     // two-step kernel: tile order, 0 = row-major, P > 0 = XCD panels of P tile columns
 };
+
+// Workgroups are dealt to the 8 XCDs round-robin.  This renumbering gives
+// each XCD one contiguous range of positions.
+__device__ __forceinline__ int xcd_contiguous(int bid, int nblocks)
+{
+    constexpr int NXCD = 8;
+    const int xcd = bid % NXCD, local = bid / NXCD;
+    const int per = nblocks / NXCD, rem = nblocks % NXCD;
+    return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
+}
+
+// Tile of workgroup `bid` in panel order: the lattice's tile columns are cut
+// into panels of P columns (the last may be narrower), each walked row by row
+// from the top, and each XCD takes one contiguous run of that order.  A tile's
+// vertical neighbour is then P positions away on the same XCD, so the halo
+// rows they share are still in that XCD's L2.
+__device__ __forceinline__ void panel_tile(int bid, int nblocks, int tiles_x, int P, int& tx, int& ty)
+{
+    const int pos = xcd_contiguous(bid, nblocks);
+    const int tiles_y = nblocks / tiles_x;
+    const int full = tiles_x / P, per_panel = P * tiles_y;
+    const int panel = pos / per_panel;
+    if (panel < full) {
+        const int w = pos - panel * per_panel;
+        ty = w / P;
+        tx = panel * P + w % P;
+    } else {
+        const int w = pos - full * per_panel, pw = tiles_x - full * P;
+        ty = w / pw;
+        tx = full * P + w % pw;
+    }
+}
 
 template <typename C> struct Coef {
     C omega;   // 1/tau
@@ -159,13 +192,19 @@ template <typename C> struct Coef {
 // drho, which restores conservation up to unbiased rounding:
 //   t_x = j_x / 2 - (t_5 - t_6),  t_y = j_y / 2 - (t_5 + t_6)  (both j / 3),
 //   q_0 = drho - 2 (s_x + s_y + s_5 + s_6)                      (w_0 (...)).
+//
+// 1/rho enters only the terms quadratic in u, so FP32 takes the hardware
+// reciprocal (1 ulp) instead of a correctly rounded division; FP64 divides.
+__device__ __forceinline__ float reciprocal(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double reciprocal(double x) { return 1.0 / x; }
+
 template <int SCHEME, typename T, typename C = typename Storage<T>::C>
 __device__ __forceinline__ void collide(C d[9], const Coef<C>& k)
 {
     const C drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
     const C jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
     const C jy = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
-    const C inv = C(1) / (C(1) + drho);
+    const C inv = reciprocal(C(1) + drho);
     const C ux = jx * inv, uy = jy * inv;
     const C base = drho - C(1.5) * (jx * ux + jy * uy);
 
@@ -197,9 +236,11 @@ __device__ __forceinline__ void collide(C d[9], const Coef<C>& k)
         for (int a = 0; a < 9; ++a) d[a] = d[a] + k.omega * (q[a] - d[a]);
     } else {
         // Group sums of Eq. (sigma1-2-0): C_1 over the axis links, C_2 over the
-        // diagonal links, each sum_k (-1)^k (f_k - f^eq_k) / 4.
-        const C c1 = C(0.25) * (((d[2] - q[2]) + (d[4] - q[4])) - ((d[1] - q[1]) + (d[3] - q[3])));
-        const C c2 = C(0.25) * (((d[6] - q[6]) + (d[8] - q[8])) - ((d[5] - q[5]) + (d[7] - q[7])));
+        // diagonal links, each sum_k (-1)^k (f_k - f^eq_k) / 4.  The odd parts
+        // cancel in the equilibrium's share (q_2 + q_4 - q_1 - q_3 = 2 (s_y - s_x),
+        // q_6 + q_8 - q_5 - q_7 = 2 (s_6 - s_5)).
+        const C c1 = C(0.25) * ((d[2] + d[4]) - (d[1] + d[3])) - C(0.5) * (sy - sx);
+        const C c2 = C(0.25) * ((d[6] + d[8]) - (d[5] + d[7])) - C(0.5) * (s6 - s5);
         if constexpr (SCHEME == SMRT) {
             // Eq. (SmrtLBM-1): f*_a = f^eq_a + (-1)^a (1 - 1/tau) C_g(a)
             const C g1 = k.a * c1, g2 = k.a * c2;
@@ -240,24 +281,69 @@ __device__ __forceinline__ void collide(C d[9], const Coef<C>& k)
     d[0] = drho - (((d[1] + d[2]) + (d[3] + d[4])) + ((d[5] + d[6]) + (d[7] + d[8])));
 }
 
+// Interior pulls and stores address each direction's plane through a
+// workgroup-uniform base pointer held in scalar registers plus one per-lane
+// 32-bit byte offset shared by all nine directions; the load/store
+// instructions add the two themselves, so no per-access 64-bit address
+// arithmetic remains.  The bases are rebased to a row row0 of the workgroup's
+// tile, which keeps the offsets to a few rows.
+template <typename T> using global_ptr = __attribute__((address_space(1))) T*;
+
+// Pins a workgroup-uniform pointer in scalar registers.  The empty asm emits
+// no instruction; it only stops the compiler from folding the base into every
+// lane's address.
+template <typename T> __device__ __forceinline__ global_ptr<T> scalar_base(T* p)
+{
+    global_ptr<T> q = (global_ptr<T>)p;
+    asm("" : "+s"(q));
+    return q;
+}
+
+template <typename T> struct PullBases {
+    global_ptr<const T> p[9]; // plane a, row row0, shifted by -e_a
+    int row0;
+};
+
+// Bases for pulls into nodes (x, y) with y - 1 >= row0.
+template <typename T>
+__device__ __forceinline__ PullBases<T> pull_bases(const T* __restrict__ src, const Geom& g, int row0)
+{
+    PullBases<T> b;
+    b.row0 = row0;
+#pragma unroll
+    for (int a = 0; a < 9; ++a)
+        b.p[a] = scalar_base(src + (int64_t)a * g.plane + (int64_t)(row0 + 1 - EY[a]) * g.pitch + (1 - EX[a]));
+    return b;
+}
+
 // Pull of the nine incoming populations of an interior node: every source
 // x - e_a lies inside the lattice.
 template <typename T>
-__device__ __forceinline__ void gather_interior(const T* __restrict__ src, const Geom& g, int x, int y,
+__device__ __forceinline__ void gather_interior(const PullBases<T>& b, const Geom& g, int x, int y,
                                                 typename Storage<T>::C d[9])
 {
-    using S = Storage<T>;
-    const T* p = src + (int64_t)y * g.pitch + x;
-    const int64_t P = g.plane, R = g.pitch;
-    d[0] = S::load(p, 0);
-    d[1] = S::load(p + 1 * P - 1, 1);
-    d[2] = S::load(p + 2 * P - R, 2);
-    d[3] = S::load(p + 3 * P + 1, 3);
-    d[4] = S::load(p + 4 * P + R, 4);
-    d[5] = S::load(p + 5 * P - R - 1, 5);
-    d[6] = S::load(p + 6 * P - R + 1, 6);
-    d[7] = S::load(p + 7 * P + R + 1, 7);
-    d[8] = S::load(p + 8 * P + R - 1, 8);
+    const uint32_t off = (uint32_t)(((y - 1 - b.row0) * g.pitch + (x - 1)) * (int)sizeof(T));
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        const global_ptr<const char> q = (global_ptr<const char>)b.p[a] + off;
+        d[a] = Storage<T>::load((const T*)(global_ptr<const T>)q, a);
+    }
+}
+
+template <typename T> struct StoreBases {
+    global_ptr<T> p[9]; // plane a, row row0
+    int row0;
+};
+
+// Bases for stores to nodes (x, y) with y >= row0.
+template <typename T>
+__device__ __forceinline__ StoreBases<T> store_bases(T* __restrict__ dst, const Geom& g, int row0)
+{
+    StoreBases<T> b;
+    b.row0 = row0;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) b.p[a] = scalar_base(dst + (int64_t)a * g.plane + (int64_t)row0 * g.pitch);
+    return b;
 }
 
 // Pull at a node on the outer ring.  Periodic: sources wrap around.  Cavity:
@@ -273,7 +359,7 @@ __device__ __forceinline__ void gather_edge(const T* __restrict__ src, const Geo
 {
     using S = Storage<T>;
     using C = typename Storage<T>::C;
-    const int own = y * g.pitch + x; // one plane never exceeds 2^31 elements
+    const int64_t own = (int64_t)y * g.pitch + x; // a plane may exceed 2^31 elements
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         int sx = x - EX[a], sy = y - EY[a];
@@ -281,11 +367,11 @@ __device__ __forceinline__ void gather_edge(const T* __restrict__ src, const Geo
         if constexpr (BC == PERIODIC) {
             sx = sx < 0 ? sx + g.nx : (sx >= g.nx ? sx - g.nx : sx);
             sy = sy < 0 ? sy + g.ny : (sy >= g.ny ? sy - g.ny : sy);
-            d[a] = S::load(plane_a + (sy * g.pitch + sx), a);
+            d[a] = S::load(plane_a + ((int64_t)sy * g.pitch + sx), a);
         } else {
             const T* plane_o = src + OPP[a] * g.plane;
             const bool inside = (unsigned)sx < (unsigned)g.nx && (unsigned)sy < (unsigned)g.ny;
-            const T* p = inside ? plane_a + (sy * g.pitch + sx) : plane_o + own;
+            const T* p = inside ? plane_a + ((int64_t)sy * g.pitch + sx) : plane_o + own;
             // a and OPP[a] share a weight class, hence a storage scale
             const C v = S::load(p, a);
             d[a] = (!inside && sy == g.ny) ? v + C(EX[a]) * lid : v;
@@ -293,13 +379,17 @@ __device__ __forceinline__ void gather_edge(const T* __restrict__ src, const Geo
     }
 }
 
+// Store of the nine post-collision populations of node (x, y).
 template <typename T>
-__device__ __forceinline__ void scatter_store(T* __restrict__ dst, const Geom& g, int x, int y,
+__device__ __forceinline__ void scatter_store(const StoreBases<T>& b, const Geom& g, int x, int y,
                                               const typename Storage<T>::C d[9])
 {
-    T* p = dst + (int64_t)y * g.pitch + x;
+    const uint32_t off = (uint32_t)(((y - b.row0) * g.pitch + x) * (int)sizeof(T));
 #pragma unroll
-    for (int a = 0; a < 9; ++a) Storage<T>::store(p + a * g.plane, a, d[a]);
+    for (int a = 0; a < 9; ++a) {
+        const global_ptr<char> q = (global_ptr<char>)b.p[a] + off;
+        Storage<T>::store((T*)(global_ptr<T>)q, a, d[a]);
+    }
 }
 
 // One time step.  Block (bx, by) threads; each thread updates `rows` nodes
@@ -318,7 +408,10 @@ __global__ void __launch_bounds__(1024) stream_collide(const T* __restrict__ src
     const int tx = tile % g.tiles_x, ty = tile / g.tiles_x;
     const int x = tx * g.bx + threadIdx.x;
     if (x >= g.nx) return;
-    const int y0 = ty * g.by * g.rows + threadIdx.y;
+    const int ytile = ty * g.by * g.rows; // first row of the tile
+    const PullBases<T> pb = pull_bases(src, g, ytile > 0 ? ytile - 1 : 0);
+    const StoreBases<T> sb = store_bases(dst, g, ytile);
+    const int y0 = ytile + threadIdx.y;
     for (int r = 0; r < g.rows; ++r) {
         const int y = y0 + r * g.by;
         if (y >= g.ny) break;
@@ -327,9 +420,9 @@ __global__ void __launch_bounds__(1024) stream_collide(const T* __restrict__ src
         if (edge)
             gather_edge<T, BC>(src, g, x, y, d, k.lid);
         else
-            gather_interior<T>(src, g, x, y, d);
+            gather_interior<T>(pb, g, x, y, d);
         collide<SCHEME, T>(d, k);
-        scatter_store<T>(dst, g, x, y, d);
+        scatter_store<T>(sb, g, x, y, d);
     }
 }
 
@@ -363,6 +456,7 @@ __device__ __forceinline__ void x2_phase1(const T* __restrict__ src, const Geom&
 {
     using Tl = X2Tile<T, TX, TY>;
     using C = typename Storage<T>::C;
+    const PullBases<T> pb = pull_bases(src, g, Y0 > 1 ? Y0 - 2 : 0);
     C d[Tl::P1][9];
     bool live[Tl::P1];
 #pragma unroll
@@ -371,9 +465,13 @@ __device__ __forceinline__ void x2_phase1(const T* __restrict__ src, const Geom&
         const int lx = i % Tl::RX, ly = i / Tl::RX;
         int x = X0 - 1 + lx, y = Y0 - 1 + ly;
         if constexpr (BC == PERIODIC) {
+            // Ring nodes past column nx or row ny feed no output of the tile;
+            // skipping them leaves only wrapped nodes on the lattice's outer
+            // ring (x or y in {0, n - 1}), which take the edge path, so every
+            // interior pull has y - 1 >= Y0 - 2, the rows its bases start at.
+            live[j] = i < Tl::RX * Tl::RY && x <= g.nx && y <= g.ny;
             x = x < 0 ? x + g.nx : (x >= g.nx ? x - g.nx : x);
             y = y < 0 ? y + g.ny : (y >= g.ny ? y - g.ny : y);
-            live[j] = i < Tl::RX * Tl::RY;
         } else {
             live[j] = i < Tl::RX * Tl::RY && (unsigned)x < (unsigned)g.nx && (unsigned)y < (unsigned)g.ny;
         }
@@ -382,7 +480,7 @@ __device__ __forceinline__ void x2_phase1(const T* __restrict__ src, const Geom&
             if (edge)
                 gather_edge<T, BC>(src, g, x, y, d[j], k.lid);
             else
-                gather_interior<T>(src, g, x, y, d[j]);
+                gather_interior<T>(pb, g, x, y, d[j]);
         }
     }
 #pragma unroll
@@ -404,6 +502,7 @@ __device__ __forceinline__ void x2_phase2(T* __restrict__ dst, const Geom& g, co
                                           int X0, int Y0, const X2Tile<T, TX, TY>& sh)
 {
     using C = typename Storage<T>::C;
+    const StoreBases<T> sb = store_bases(dst, g, Y0);
     for (int i = threadIdx.x; i < TX * TY; i += X2_THREADS) {
         const int tx = i % TX, ty = i / TX;
         const int x = X0 + tx, y = Y0 + ty;
@@ -411,19 +510,21 @@ __device__ __forceinline__ void x2_phase2(T* __restrict__ dst, const Geom& g, co
         const int lx = tx + 1, ly = ty + 1;
         C d[9];
 #pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            const C pulled = sh.mid[a][ly - EY[a]][lx - EX[a]];
-            if constexpr (BC == CAVITY) {
-                const int sx = x - EX[a], sy = y - EY[a];
-                const bool inside = (unsigned)sx < (unsigned)g.nx && (unsigned)sy < (unsigned)g.ny;
-                const C own = sh.mid[OPP[a]][ly][lx];
-                d[a] = inside ? pulled : ((sy == g.ny) ? own + C(EX[a]) * k.lid : own);
-            } else {
-                d[a] = pulled;
+        for (int a = 0; a < 9; ++a) d[a] = sh.mid[a][ly - EY[a]][lx - EX[a]];
+        if constexpr (BC == CAVITY) {
+            // only lanes on the lattice's outer ring have sources beyond a wall
+            if ((x == 0) | (x == g.nx - 1) | (y == 0) | (y == g.ny - 1)) {
+#pragma unroll
+                for (int a = 1; a < 9; ++a) {
+                    const int sx = x - EX[a], sy = y - EY[a];
+                    const bool inside = (unsigned)sx < (unsigned)g.nx && (unsigned)sy < (unsigned)g.ny;
+                    const C own = sh.mid[OPP[a]][ly][lx];
+                    d[a] = inside ? d[a] : ((sy == g.ny) ? own + C(EX[a]) * k.lid : own);
+                }
             }
         }
         collide<SCHEME, T>(d, k);
-        scatter_store<T>(dst, g, x, y, d);
+        scatter_store<T>(sb, g, x, y, d);
     }
 }
 
@@ -432,7 +533,10 @@ __global__ void __launch_bounds__(X2_THREADS) stream_collide_x2(const T* __restr
                                                                Geom g, Coef<typename Storage<T>::C> k)
 {
     __shared__ X2Tile<T, TX, TY> sh;
-    const int X0 = (blockIdx.x % g.tiles_x) * TX, Y0 = (blockIdx.x / g.tiles_x) * TY;
+    int tx = (int)blockIdx.x % g.tiles_x, ty = (int)blockIdx.x / g.tiles_x;
+    if (g.panel > 0)
+        panel_tile(blockIdx.x, gridDim.x, g.tiles_x, g.panel, tx, ty);
+    const int X0 = tx * TX, Y0 = ty * TY;
     x2_phase1<T, SCHEME, BC, TX, TY>(src, g, k, X0, Y0, sh);
     __syncthreads();
     x2_phase2<T, SCHEME, BC, TX, TY>(dst, g, k, X0, Y0, sh);

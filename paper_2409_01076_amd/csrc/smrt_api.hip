@@ -199,6 +199,7 @@ struct smrt_ctx {
     int bx = 256, by = 1, rows = 1;
     int fused = 1;                 // time steps per launch (1, or 2 with the LDS-blocked kernel)
     int fused_cols = 64, fused_rows = 8; // tile of the two-step kernel
+    int panel = 0;                 // two-step kernel: tile order (0 = row-major)
 
     void* buffer(int which) const { return ws + (which == 0 ? L.off_a : L.off_b); }
     double* snap_x() const { return reinterpret_cast<double*>(ws + L.off_snap_x); }
@@ -217,6 +218,7 @@ struct smrt_ctx {
         g.by = by;
         g.rows = rows;
         g.tiles_x = (p.nx + bx - 1) / bx;
+        g.panel = panel;
         return g;
     }
     int64_t nodes() const { return (int64_t)p.nx * p.ny; }
@@ -434,6 +436,10 @@ int smrt_create(const smrt_params* p, void* dev_ws, size_t ws_bytes, smrt_ctx** 
             c->fused_cols = 64;
             c->fused_rows = tiles8 >= 4096 ? 8 : 4;
             if (p->boundary == SMRT_CAVITY || (p->nx >= 66 && p->ny >= c->fused_rows + 2)) c->fused = 2;
+            // XCD panels of 8 tile columns: FP32 reads drop from 1.67x to
+            // 1.08x the algorithmic bytes on 4096^2 and the launch gets 3-4%
+            // faster; 16-bit storage measured 4% slower with panels.
+            c->panel = p->storage == SMRT_F32 ? 8 : 0;
         }
         if (p->nx >= 512) {
             c->bx = 512; c->by = 1;
@@ -631,6 +637,14 @@ int smrt_set_steps_per_launch(smrt_ctx* c, int32_t steps, int32_t tile_cols, int
 }
 
 int32_t smrt_get_steps_per_launch(const smrt_ctx* c) { return c ? c->fused : -1; }
+
+int smrt_set_tile_order(smrt_ctx* c, int32_t panel_cols)
+{
+    if (!c) return fail(SMRT_EINVAL, "context is NULL");
+    if (panel_cols < 0) return fail(SMRT_EINVAL, "panel width must be >= 0 (got %d)", panel_cols);
+    c->panel = panel_cols;
+    return SMRT_OK;
+}
 
 int smrt_synchronize(smrt_ctx* c)
 {

@@ -347,7 +347,7 @@ int check_index(const smrt_batch* b, int32_t index)
 
 smrt::Geom geom_of(const smrt::CavityDesc& c)
 {
-    smrt::Geom g;
+    smrt::Geom g{};
     g.nx = c.nx;
     g.ny = c.ny;
     g.pitch = c.pitch;

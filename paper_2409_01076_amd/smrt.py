@@ -23,7 +23,7 @@ EXPORTED = (
     "smrt_workspace_bytes", "smrt_create", "smrt_init_fields", "smrt_set_populations",
     "smrt_get_populations", "smrt_step", "smrt_moments", "smrt_residual", "smrt_mass",
     "smrt_steps_done", "smrt_tau", "smrt_set_launch", "smrt_set_steps_per_launch",
-    "smrt_get_steps_per_launch",
+    "smrt_get_steps_per_launch", "smrt_set_tile_order",
     "smrt_synchronize", "smrt_destroy",
     "smrt_last_error", "smrt_copy_kernel",
     "smrt_batch_workspace_bytes", "smrt_batch_create", "smrt_batch_step", "smrt_batch_run",
@@ -109,6 +109,7 @@ def load():
         "smrt_set_launch": (ctypes.c_int, [vp, i32, i32, i32]),
         "smrt_set_steps_per_launch": (ctypes.c_int, [vp, i32, i32, i32]),
         "smrt_get_steps_per_launch": (i32, [vp]),
+        "smrt_set_tile_order": (ctypes.c_int, [vp, i32]),
         "smrt_synchronize": (ctypes.c_int, [vp]),
         "smrt_destroy": (None, [vp]),
         "smrt_last_error": (ctypes.c_char_p, []),
@@ -338,6 +339,11 @@ class Solver:
         """1, or 2 for the two-step LDS-blocked kernel (FP32/16-bit storage);
         tile 64 x {4, 8, 16} or 128 x {4, 8} (0 = default 64 x 8)."""
         _check(load().smrt_set_steps_per_launch(self._ctx, int(steps), int(tile_cols), int(tile_rows)))
+
+    def set_tile_order(self, panel_cols):
+        """Two-step tile order: 0 = row-major, P > 0 = XCD panels of P tile
+        columns (same results, different L2 reuse)."""
+        _check(load().smrt_set_tile_order(self._ctx, int(panel_cols)))
 
     def synchronize(self):
         _check(load().smrt_synchronize(self._ctx))

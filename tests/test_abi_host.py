@@ -84,6 +84,7 @@ def test_null_context_calls_fail_cleanly():
     out = ctypes.c_double()
     assert lib.smrt_residual(None, ctypes.byref(out)) == smrt.EINVAL
     assert lib.smrt_set_launch(None, 64, 4, 1) == smrt.EINVAL
+    assert lib.smrt_set_tile_order(None, 8) == smrt.EINVAL
     assert lib.smrt_copy_kernel(None, None, 16, None) == smrt.EINVAL
     assert "NULL" in lib.smrt_last_error().decode()
 

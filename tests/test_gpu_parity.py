@@ -383,6 +383,26 @@ def test_two_step_kernel_small_cavities(smrt, nx, ny):
     assert np.array_equal(outs[0], outs[1])
 
 
+@pytest.mark.parametrize("boundary", ["periodic", "cavity"])
+@pytest.mark.parametrize("tile", [(64, 8), (128, 4)])
+def test_tile_order_does_not_change_results(smrt, boundary, tile):
+    """Every tile order (row-major, XCD panels of several widths, ragged last
+    panel, a panel wider than the lattice) computes each tile exactly once."""
+    nx, ny, steps = 203, 77, 20
+    f0 = inputs.perturbed_populations(nx, ny, eps=0.03, seed=6)
+    outs = []
+    for panel in (0, 1, 3, 8, 1000):
+        with smrt.Solver(nx, ny, scheme="smrt", boundary=boundary, storage="f32", tau=0.56,
+                         u_lid=0.1 if boundary == "cavity" else 0.0) as s:
+            s.set_populations(to_dev(f0, torch.float64))
+            s.set_steps_per_launch(2, tile_rows=tile[1], tile_cols=tile[0])
+            s.set_tile_order(panel)
+            s.step(steps)
+            outs.append(s.populations(torch.float64).cpu().numpy())
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
+
+
 def test_two_step_kernel_against_oracle(smrt):
     n, u, steps = 96, 0.1, 600
     with smrt.Solver(n, n, scheme="smrt", boundary="cavity", storage="f32", re=300.0, u_lid=u) as s:
@@ -400,6 +420,8 @@ def test_two_step_kernel_rejects_unsupported(smrt):
             s.set_steps_per_launch(2)          # periodic, nx < 66
         with pytest.raises(smrt.SmrtError):
             s.set_steps_per_launch(2, tile_rows=16, tile_cols=128)   # tile not offered
+        with pytest.raises(smrt.SmrtError):
+            s.set_tile_order(-1)
     with smrt.Solver(128, 128, scheme="smrt", boundary="cavity", storage="f64", tau=0.7, u_lid=0.1) as s:
         with pytest.raises(smrt.SmrtError):
             s.set_steps_per_launch(2)          # FP64 storage
