@@ -160,11 +160,13 @@ int smrt_set_launch(smrt_ctx* c, int32_t bx, int32_t by, int32_t rows);
 /* Time steps per kernel launch: 1, or 2 with the LDS-blocked kernel that
  * keeps the intermediate step on chip, halving the HBM traffic per
  * node-update (FP32 and 16-bit storage only).  Tile of the two-step kernel:
- * tile_cols x tile_rows in {64 x 4, 64 x 8, 64 x 16, 128 x 4, 128 x 8}
- * (0 = 64 x 8); a periodic lattice needs nx >= tile_cols + 2 and
- * ny >= tile_rows + 2.  Per node the arithmetic is unchanged: results are
- * bitwise those of single-step launches.  Default at creation: 2 steps with a
- * 64 x 8 tile (64 x 4 below 4096 tiles) wherever applicable, else 1.  An odd
+ * tile_cols x tile_rows in {64 x 4, 64 x 8, 64 x 16, 64 x 32, 128 x 4,
+ * 128 x 8} (0 = 64 x 8); tiles of 1024 nodes or more run 512 threads per
+ * workgroup, smaller ones 256.  A periodic lattice needs nx >= tile_cols + 2
+ * and ny >= tile_rows + 2.  Per node the arithmetic is unchanged: results are
+ * bitwise those of single-step launches.  Default at creation: 2 steps
+ * wherever applicable, with a 64 x 16 tile while that gives >= 4096 tiles,
+ * else 64 x 32 while that gives >= 512, else 64 x 4; otherwise 1.  An odd
  * step count ends with one single-step launch.  SMRT_EINVAL if not
  * applicable. */
 int smrt_set_steps_per_launch(smrt_ctx* c, int32_t steps, int32_t tile_cols, int32_t tile_rows);
@@ -178,7 +180,7 @@ int32_t smrt_get_steps_per_launch(const smrt_ctx* c);
  * into panels of P, each walked top to bottom, and each of the GPU's 8 XCDs
  * takes one contiguous run of that order, so neighbouring tiles share an L2
  * and the halo rows and columns they both read are fetched from memory once.
- * Default at creation: 8 for FP32 storage, 0 otherwise.  SMRT_EINVAL for
+ * Default at creation: 8.  SMRT_EINVAL for
  * c == NULL or panel_cols < 0. */
 int smrt_set_tile_order(smrt_ctx* c, int32_t panel_cols);
 
@@ -253,8 +255,10 @@ int smrt_batch_run(smrt_batch* b, double tol, int64_t window, int64_t max_steps,
 
 /* Chooses the tile shape (bx, by) and the number of resident workgroups of
  * the batch kernel by timing `steps` real steps (an even number >= 2) of each
- * candidate; keeps the fastest.  chosen (host [3], may be NULL) receives
- * bx, by and the grid size.  The trial steps advance every running cavity. */
+ * candidate (the one-step shapes, and except for FP64 storage the two-step
+ * kernel with 64 x 4, 64 x 8 and 64 x 16 tiles); keeps the fastest.  chosen
+ * (host [3], may be NULL) receives bx, by and the grid size.  The trial steps
+ * advance every running cavity. */
 int smrt_batch_autotune(smrt_batch* b, int32_t steps, int32_t* chosen);
 
 /* Fields of cavity `index` (dense device arrays [ny][nx], F32 or F64; any may

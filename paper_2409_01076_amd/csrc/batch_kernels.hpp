@@ -103,15 +103,15 @@ __global__ void __launch_bounds__(1024) batch_stream_collide(const CavityDesc* _
 
 // Two time steps of every listed tile per launch: the batch form of
 // stream_collide_x2 (same two phases through LDS), for tiles of TX x TY
-// nodes and X2_THREADS threads.  Cavity walls need no wrap, so any size works.
-template <typename T, int SCHEME, int TX, int TY>
-__global__ void __launch_bounds__(X2_THREADS) batch_stream_collide_x2(const CavityDesc* __restrict__ cav,
-                                                                     const int2* __restrict__ tiles,
-                                                                     const int* __restrict__ ntiles_p,
-                                                                     T* __restrict__ base, int parity)
+// nodes and NT threads.  Cavity walls need no wrap, so any size works.
+template <typename T, int SCHEME, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT) batch_stream_collide_x2(const CavityDesc* __restrict__ cav,
+                                                              const int2* __restrict__ tiles,
+                                                              const int* __restrict__ ntiles_p,
+                                                              T* __restrict__ base, int parity)
 {
     using C = typename Storage<T>::C;
-    __shared__ X2Tile<T, TX, TY> sh;
+    __shared__ X2Tile<T, TX, TY, NT> sh;
     const int ntiles = *ntiles_p;
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int2 tt = tiles[t];
@@ -131,9 +131,9 @@ __global__ void __launch_bounds__(X2_THREADS) batch_stream_collide_x2(const Cavi
         T* dst = base + (parity ? c.off[0] : c.off[1]);
         const Coef<C> k = coef_of<C>(c);
         const int X0 = (ti % c.tiles_x) * TX, Y0 = (ti / c.tiles_x) * TY;
-        x2_phase1<T, SCHEME, CAVITY, TX, TY>(src, g, k, X0, Y0, sh);
+        x2_phase1<T, SCHEME, CAVITY, TX, TY, NT>(src, g, k, X0, Y0, sh);
         __syncthreads();
-        x2_phase2<T, SCHEME, CAVITY, TX, TY>(dst, g, k, X0, Y0, sh);
+        x2_phase2<T, SCHEME, CAVITY, TX, TY, NT>(dst, g, k, X0, Y0, sh);
         __syncthreads(); // the next tile reuses the LDS
     }
 }

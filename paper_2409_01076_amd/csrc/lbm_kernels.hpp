@@ -147,15 +147,18 @@ __device__ __forceinline__ int xcd_contiguous(int bid, int nblocks)
     return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
 }
 
-// Tile of workgroup `bid` in panel order: the lattice's tile columns are cut
-// into panels of P columns (the last may be narrower), each walked row by row
-// from the top, and each XCD takes one contiguous run of that order.  A tile's
-// vertical neighbour is then P positions away on the same XCD, so the halo
-// rows they share are still in that XCD's L2.
-__device__ __forceinline__ void panel_tile(int bid, int nblocks, int tiles_x, int P, int& tx, int& ty)
+// Tile at position `pos` of the panel order: the lattice's tile columns are
+// cut into panels of P columns (the last may be narrower), each walked row by
+// row from the top.  With each XCD taking one contiguous run of positions, a
+// tile's vertical neighbour is P positions away on the same XCD, so the halo
+// rows they share are still in that XCD's L2.  P = 0: row-major.
+__device__ __forceinline__ void panel_tile(int pos, int tiles_x, int tiles_y, int P, int& tx, int& ty)
 {
-    const int pos = xcd_contiguous(bid, nblocks);
-    const int tiles_y = nblocks / tiles_x;
+    if (P <= 0) {
+        tx = pos % tiles_x;
+        ty = pos / tiles_x;
+        return;
+    }
     const int full = tiles_x / P, per_panel = P * tiles_y;
     const int panel = pos / per_panel;
     if (panel < full) {
@@ -437,31 +440,34 @@ __global__ void __launch_bounds__(1024) stream_collide(const T* __restrict__ src
 // results are bitwise those of two one-step launches.
 constexpr int X2_THREADS = 256;
 
-template <typename T, int TX, int TY> struct X2Tile {
+template <typename T, int TX, int TY, int NT = X2_THREADS> struct X2Tile {
     using C = typename Storage<T>::C;
     static constexpr int RX = TX + 2, RY = TY + 2;
-    static constexpr int P1 = (RX * RY + X2_THREADS - 1) / X2_THREADS; // ring nodes per thread
-    static constexpr int P2 = (TX * TY + X2_THREADS - 1) / X2_THREADS; // tile nodes per thread
+    static constexpr int P1 = (RX * RY + NT - 1) / NT; // ring nodes per thread
+    static constexpr int P2 = (TX * TY + NT - 1) / NT; // tile nodes per thread
     C mid[9][RY][RX];                                                  // step t+1 (LDS)
 };
 
-// Phase 1.  Each thread first issues the loads of all its ring nodes, then
-// collides them, so up to 9 P1 loads per lane are in flight together.  A
-// periodic ring wraps once (nx >= TX + 2, ny >= TY + 2); a cavity ring
-// skips the nodes beyond the walls.
-template <typename T, int SCHEME, int BC, int TX, int TY>
-__device__ __forceinline__ void x2_phase1(const T* __restrict__ src, const Geom& g,
-                                          const Coef<typename Storage<T>::C>& k, int X0, int Y0,
-                                          X2Tile<T, TX, TY>& sh)
-{
-    using Tl = X2Tile<T, TX, TY>;
+// Phase 1 in two halves.  x2_load issues the loads of all ring nodes of the
+// thread (up to 9 P1 loads per lane in flight together); x2_collide collides
+// them and writes step t+1 to LDS.  A periodic ring wraps once (nx >= TX + 2,
+// ny >= TY + 2); a cavity ring skips the nodes beyond the walls.
+template <typename T, int TX, int TY, int NT = X2_THREADS> struct X2Ring {
     using C = typename Storage<T>::C;
+    static constexpr int P1 = X2Tile<T, TX, TY, NT>::P1;
+    C d[P1][9];
+    bool live[P1];
+};
+
+template <typename T, int BC, int TX, int TY, int NT = X2_THREADS>
+__device__ __forceinline__ void x2_load(const T* __restrict__ src, const Geom& g, typename Storage<T>::C lid,
+                                        int X0, int Y0, X2Ring<T, TX, TY, NT>& r)
+{
+    using Tl = X2Tile<T, TX, TY, NT>;
     const PullBases<T> pb = pull_bases(src, g, Y0 > 1 ? Y0 - 2 : 0);
-    C d[Tl::P1][9];
-    bool live[Tl::P1];
 #pragma unroll
     for (int j = 0; j < Tl::P1; ++j) {
-        const int i = threadIdx.x + j * X2_THREADS;
+        const int i = threadIdx.x + j * NT;
         const int lx = i % Tl::RX, ly = i / Tl::RX;
         int x = X0 - 1 + lx, y = Y0 - 1 + ly;
         if constexpr (BC == PERIODIC) {
@@ -469,41 +475,58 @@ __device__ __forceinline__ void x2_phase1(const T* __restrict__ src, const Geom&
             // skipping them leaves only wrapped nodes on the lattice's outer
             // ring (x or y in {0, n - 1}), which take the edge path, so every
             // interior pull has y - 1 >= Y0 - 2, the rows its bases start at.
-            live[j] = i < Tl::RX * Tl::RY && x <= g.nx && y <= g.ny;
+            r.live[j] = i < Tl::RX * Tl::RY && x <= g.nx && y <= g.ny;
             x = x < 0 ? x + g.nx : (x >= g.nx ? x - g.nx : x);
             y = y < 0 ? y + g.ny : (y >= g.ny ? y - g.ny : y);
         } else {
-            live[j] = i < Tl::RX * Tl::RY && (unsigned)x < (unsigned)g.nx && (unsigned)y < (unsigned)g.ny;
+            r.live[j] = i < Tl::RX * Tl::RY && (unsigned)x < (unsigned)g.nx && (unsigned)y < (unsigned)g.ny;
         }
-        if (live[j]) {
+        if (r.live[j]) {
             const bool edge = (x == 0) | (x == g.nx - 1) | (y == 0) | (y == g.ny - 1);
             if (edge)
-                gather_edge<T, BC>(src, g, x, y, d[j], k.lid);
+                gather_edge<T, BC>(src, g, x, y, r.d[j], lid);
             else
-                gather_interior<T>(pb, g, x, y, d[j]);
+                gather_interior<T>(pb, g, x, y, r.d[j]);
         }
     }
+}
+
+template <typename T, int SCHEME, int TX, int TY, int NT = X2_THREADS>
+__device__ __forceinline__ void x2_collide(const Coef<typename Storage<T>::C>& k, X2Ring<T, TX, TY, NT>& r,
+                                           X2Tile<T, TX, TY, NT>& sh)
+{
+    using Tl = X2Tile<T, TX, TY, NT>;
 #pragma unroll
     for (int j = 0; j < Tl::P1; ++j) {
-        if (!live[j]) continue;
-        const int i = threadIdx.x + j * X2_THREADS;
+        if (!r.live[j]) continue;
+        const int i = threadIdx.x + j * NT;
         const int lx = i % Tl::RX, ly = i / Tl::RX;
-        collide<SCHEME, T>(d[j], k);
-        if constexpr (Storage<T>::kRounds) d[j][0] = Storage<T>::stored_value(d[j][0], 0);
+        collide<SCHEME, T>(r.d[j], k);
+        if constexpr (Storage<T>::kRounds) r.d[j][0] = Storage<T>::stored_value(r.d[j][0], 0);
 #pragma unroll
-        for (int a = 0; a < 9; ++a) sh.mid[a][ly][lx] = d[j][a];
+        for (int a = 0; a < 9; ++a) sh.mid[a][ly][lx] = r.d[j][a];
     }
+}
+
+template <typename T, int SCHEME, int BC, int TX, int TY, int NT = X2_THREADS>
+__device__ __forceinline__ void x2_phase1(const T* __restrict__ src, const Geom& g,
+                                          const Coef<typename Storage<T>::C>& k, int X0, int Y0,
+                                          X2Tile<T, TX, TY, NT>& sh)
+{
+    X2Ring<T, TX, TY, NT> r;
+    x2_load<T, BC, TX, TY, NT>(src, g, k.lid, X0, Y0, r);
+    x2_collide<T, SCHEME, TX, TY, NT>(k, r, sh);
 }
 
 // Phase 2: pull step t+1 from LDS (bounce-back from the node's own opposite
 // population where the source lies beyond a cavity wall), collide, store t+2.
-template <typename T, int SCHEME, int BC, int TX, int TY>
+template <typename T, int SCHEME, int BC, int TX, int TY, int NT = X2_THREADS>
 __device__ __forceinline__ void x2_phase2(T* __restrict__ dst, const Geom& g, const Coef<typename Storage<T>::C>& k,
-                                          int X0, int Y0, const X2Tile<T, TX, TY>& sh)
+                                          int X0, int Y0, const X2Tile<T, TX, TY, NT>& sh)
 {
     using C = typename Storage<T>::C;
     const StoreBases<T> sb = store_bases(dst, g, Y0);
-    for (int i = threadIdx.x; i < TX * TY; i += X2_THREADS) {
+    for (int i = threadIdx.x; i < TX * TY; i += NT) {
         const int tx = i % TX, ty = i / TX;
         const int x = X0 + tx, y = Y0 + ty;
         if (x >= g.nx || y >= g.ny) continue;
@@ -528,18 +551,19 @@ __device__ __forceinline__ void x2_phase2(T* __restrict__ dst, const Geom& g, co
     }
 }
 
-template <typename T, int SCHEME, int BC, int TX, int TY>
-__global__ void __launch_bounds__(X2_THREADS) stream_collide_x2(const T* __restrict__ src, T* __restrict__ dst,
-                                                               Geom g, Coef<typename Storage<T>::C> k)
+template <typename T, int SCHEME, int BC, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT) stream_collide_x2(const T* __restrict__ src, T* __restrict__ dst, Geom g,
+                                                        Coef<typename Storage<T>::C> k)
 {
-    __shared__ X2Tile<T, TX, TY> sh;
-    int tx = (int)blockIdx.x % g.tiles_x, ty = (int)blockIdx.x / g.tiles_x;
-    if (g.panel > 0)
-        panel_tile(blockIdx.x, gridDim.x, g.tiles_x, g.panel, tx, ty);
+    __shared__ X2Tile<T, TX, TY, NT> sh;
+    const int tiles_y = (int)gridDim.x / g.tiles_x;
+    const int pos = g.panel > 0 ? xcd_contiguous(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    int tx, ty;
+    panel_tile(pos, g.tiles_x, tiles_y, g.panel, tx, ty);
     const int X0 = tx * TX, Y0 = ty * TY;
-    x2_phase1<T, SCHEME, BC, TX, TY>(src, g, k, X0, Y0, sh);
+    x2_phase1<T, SCHEME, BC, TX, TY, NT>(src, g, k, X0, Y0, sh);
     __syncthreads();
-    x2_phase2<T, SCHEME, BC, TX, TY>(dst, g, k, X0, Y0, sh);
+    x2_phase2<T, SCHEME, BC, TX, TY, NT>(dst, g, k, X0, Y0, sh);
 }
 
 // ---------------------------------------------------------------------------

@@ -264,11 +264,24 @@ template <typename T> int launch_step(smrt_ctx* c, const void* src, void* dst)
     return SMRT_OK;
 }
 
+// Threads per two-step workgroup: 512 for tiles of 1024 nodes or more.
+constexpr int x2_threads(int tx, int ty) { return tx * ty >= 1024 ? 512 : 256; }
+
+template <typename T, int SCHEME, int BC, int TX, int TY>
+int launch_x2(smrt_ctx* c, const T* s, T* d, const smrt::Geom& g, const smrt::Coef<typename smrt::Storage<T>::C>& k,
+              int ntiles)
+{
+    constexpr int NT = x2_threads(TX, TY);
+    smrt::stream_collide_x2<T, SCHEME, BC, TX, TY, NT><<<ntiles, NT, 0, c->stream>>>(s, d, g, k);
+    return SMRT_OK;
+}
+
 template <typename T, int TX, int TY> int launch_step2_tile(smrt_ctx* c, const void* src, void* dst)
 {
     using C = typename smrt::Storage<T>::C;
     smrt::Geom g = c->geom();
     g.tiles_x = (g.nx + TX - 1) / TX;
+    g.panel = std::min(c->panel, g.tiles_x); // a wider panel is the same order, and keeps P * tiles_y in range
     const int tiles_y = (g.ny + TY - 1) / TY;
     smrt::Coef<C> k;
     const double omega = 1.0 / c->tau;
@@ -280,28 +293,24 @@ template <typename T, int TX, int TY> int launch_step2_tile(smrt_ctx* c, const v
     k.lid = (C)(c->p.boundary == SMRT_CAVITY ? c->p.u_lid / 6.0 : 0.0);
     const int64_t blocks = (int64_t)g.tiles_x * tiles_y;
     if (blocks > std::numeric_limits<int>::max()) return fail(SMRT_EINVAL, "grid too large");
+    const int n = (int)blocks;
     const T* s = static_cast<const T*>(src);
     T* d = static_cast<T*>(dst);
-    const dim3 grid((unsigned)blocks), block(smrt::X2_THREADS);
     const bool per = c->p.boundary == SMRT_PERIODIC;
     switch (c->p.scheme) {
     case SMRT_SCHEME_SRT:
-        if (per) smrt::stream_collide_x2<T, smrt::SRT, smrt::PERIODIC, TX, TY><<<grid, block, 0, c->stream>>>(s, d, g, k);
-        else smrt::stream_collide_x2<T, smrt::SRT, smrt::CAVITY, TX, TY><<<grid, block, 0, c->stream>>>(s, d, g, k);
-        break;
+        return per ? launch_x2<T, smrt::SRT, smrt::PERIODIC, TX, TY>(c, s, d, g, k, n)
+                   : launch_x2<T, smrt::SRT, smrt::CAVITY, TX, TY>(c, s, d, g, k, n);
     case SMRT_SCHEME_SMRT:
-        if (per) smrt::stream_collide_x2<T, smrt::SMRT, smrt::PERIODIC, TX, TY><<<grid, block, 0, c->stream>>>(s, d, g, k);
-        else smrt::stream_collide_x2<T, smrt::SMRT, smrt::CAVITY, TX, TY><<<grid, block, 0, c->stream>>>(s, d, g, k);
-        break;
+        return per ? launch_x2<T, smrt::SMRT, smrt::PERIODIC, TX, TY>(c, s, d, g, k, n)
+                   : launch_x2<T, smrt::SMRT, smrt::CAVITY, TX, TY>(c, s, d, g, k, n);
     default:
-        if (per) smrt::stream_collide_x2<T, smrt::TRT, smrt::PERIODIC, TX, TY><<<grid, block, 0, c->stream>>>(s, d, g, k);
-        else smrt::stream_collide_x2<T, smrt::TRT, smrt::CAVITY, TX, TY><<<grid, block, 0, c->stream>>>(s, d, g, k);
-        break;
+        return per ? launch_x2<T, smrt::TRT, smrt::PERIODIC, TX, TY>(c, s, d, g, k, n)
+                   : launch_x2<T, smrt::TRT, smrt::CAVITY, TX, TY>(c, s, d, g, k, n);
     }
-    return SMRT_OK;
 }
 
-// Two-step tiles offered: 64 x {4, 8, 16} and 128 x {4, 8}.
+// Two-step tiles offered: 64 x {4, 8, 16, 32} and 128 x {4, 8}.
 template <typename T> int launch_step2(smrt_ctx* c, const void* src, void* dst)
 {
     if (c->fused_cols == 128) {
@@ -310,6 +319,7 @@ template <typename T> int launch_step2(smrt_ctx* c, const void* src, void* dst)
     }
     if (c->fused_rows == 4) return launch_step2_tile<T, 64, 4>(c, src, dst);
     if (c->fused_rows == 16) return launch_step2_tile<T, 64, 16>(c, src, dst);
+    if (c->fused_rows == 32) return launch_step2_tile<T, 64, 32>(c, src, dst);
     return launch_step2_tile<T, 64, 8>(c, src, dst);
 }
 
@@ -429,17 +439,23 @@ int smrt_create(const smrt_params* p, void* dev_ws, size_t ws_bytes, smrt_ctx** 
         // lattice allows (512 measured best on 4096^2, within 1-2% of 256).
         // Two steps per launch wherever the LDS-blocked kernel applies (FP32
         // and 16-bit storage; periodic lattices at least a tile plus its
-        // ring): 64 x 8 tiles when that still gives >= 4096 workgroups, else
-        // 64 x 4 (measured best on 256^2 .. 4096^2).
+        // ring).  Tile, measured on 1024^2 .. 4096^2: 64 x 16 (512 threads)
+        // while that still gives >= 4096 workgroups, else 64 x 32 (512
+        // threads) while that gives >= 512, else 64 x 4; tiles in XCD panels
+        // of 8 tile columns (FP32 reads drop from 1.67x to 1.08x the
+        // algorithmic bytes).
         if (p->storage != SMRT_F64) {
-            const int64_t tiles8 = (int64_t)((p->nx + 63) / 64) * ((p->ny + 7) / 8);
+            const int64_t cols = (p->nx + 63) / 64;
             c->fused_cols = 64;
-            c->fused_rows = tiles8 >= 4096 ? 8 : 4;
+            if (cols * ((p->ny + 15) / 16) >= 4096)
+                c->fused_rows = 16;
+            else if (cols * ((p->ny + 31) / 32) >= 512)
+                c->fused_rows = 32;
+            else
+                c->fused_rows = 4;
+            if (p->boundary == SMRT_PERIODIC && p->ny < c->fused_rows + 2) c->fused_rows = 4;
             if (p->boundary == SMRT_CAVITY || (p->nx >= 66 && p->ny >= c->fused_rows + 2)) c->fused = 2;
-            // XCD panels of 8 tile columns: FP32 reads drop from 1.67x to
-            // 1.08x the algorithmic bytes on 4096^2 and the launch gets 3-4%
-            // faster; 16-bit storage measured 4% slower with panels.
-            c->panel = p->storage == SMRT_F32 ? 8 : 0;
+            c->panel = 8;
         }
         if (p->nx >= 512) {
             c->bx = 512; c->by = 1;
@@ -620,7 +636,7 @@ int smrt_set_steps_per_launch(smrt_ctx* c, int32_t steps, int32_t tile_cols, int
     if (steps != 1 && steps != 2) return fail(SMRT_EINVAL, "steps per launch must be 1 or 2 (got %d)", steps);
     if (tile_cols == 0) tile_cols = 64;
     if (tile_rows == 0) tile_rows = 8;
-    const bool ok = (tile_cols == 64 && (tile_rows == 4 || tile_rows == 8 || tile_rows == 16)) ||
+    const bool ok = (tile_cols == 64 && (tile_rows == 4 || tile_rows == 8 || tile_rows == 16 || tile_rows == 32)) ||
                     (tile_cols == 128 && (tile_rows == 4 || tile_rows == 8));
     if (!ok) return fail(SMRT_EINVAL, "two-step tile %d x %d not offered", tile_cols, tile_rows);
     if (steps == 2) {

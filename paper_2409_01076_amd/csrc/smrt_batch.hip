@@ -218,10 +218,14 @@ int upload_tables(smrt_batch* b)
     return SMRT_OK;
 }
 
+// Threads per two-step workgroup: 512 for 64 x 16 tiles, 256 for smaller.
+constexpr int two_threads(int ty) { return ty >= 16 ? 512 : 256; }
+
 template <typename T, int SCHEME, int TY>
 void launch_two_tile(smrt_batch* b, hipStream_t s, int parity, dim3 grid)
 {
-    smrt::batch_stream_collide_x2<T, SCHEME, 64, TY><<<grid, smrt::X2_THREADS, 0, s>>>(
+    constexpr int NT = two_threads(TY);
+    smrt::batch_stream_collide_x2<T, SCHEME, 64, TY, NT><<<grid, NT, 0, s>>>(
         b->desc(), b->table(), b->ntiles_dev(), reinterpret_cast<T*>(b->state()), parity);
 }
 
@@ -229,7 +233,8 @@ template <typename T, int SCHEME> void launch_typed_scheme(smrt_batch* b, hipStr
 {
     dim3 grid((unsigned)std::max(b->grid, 1));
     if (two) {
-        if (b->shape.by == 8) launch_two_tile<T, SCHEME, 8>(b, s, parity, grid);
+        if (b->shape.by == 16) launch_two_tile<T, SCHEME, 16>(b, s, parity, grid);
+        else if (b->shape.by == 8) launch_two_tile<T, SCHEME, 8>(b, s, parity, grid);
         else launch_two_tile<T, SCHEME, 4>(b, s, parity, grid);
         return;
     }
@@ -537,15 +542,16 @@ int smrt_batch_autotune(smrt_batch* b, int32_t steps, int32_t* chosen)
     bool best_two = b->two;
     int rc = SMRT_OK;
     // Candidates: every one-step shape, then (except for FP64) the two-step
-    // kernel with 64 x 4 and 64 x 8 tiles; times are per time step.
-    const int n_two = b->p.storage == SMRT_F64 ? 0 : 2;
+    // kernel with 64 x 4, 64 x 8 and 64 x 16 tiles; times are per time step.
+    static const int kTwoRows[] = {4, 8, 16};
+    const int n_two = b->p.storage == SMRT_F64 ? 0 : 3;
     for (int s = 0; s < kNumShapes + n_two && rc == SMRT_OK; ++s) {
         const bool two = s >= kNumShapes;
-        b->shape = two ? smrt::BatchLaunch{64, s == kNumShapes ? 4 : 8} : kShapes[s];
+        b->shape = two ? smrt::BatchLaunch{64, kTwoRows[s - kNumShapes]} : kShapes[s];
         b->two = two;
         rc = upload_tables(b);
         if (rc) break;
-        const int per_block_waves = two ? smrt::X2_THREADS / 64 : (b->shape.bx * b->shape.by) / 64;
+        const int per_block_waves = two ? two_threads(b->shape.by) / 64 : (b->shape.bx * b->shape.by) / 64;
         const int grids[] = {b->ntiles, cus * std::max(1, 8 / per_block_waves), cus * std::max(1, 16 / per_block_waves),
                              cus * std::max(1, 32 / per_block_waves)};
         for (int gi = 0; gi < 4; ++gi) {

@@ -337,7 +337,7 @@ class Solver:
 
     def set_steps_per_launch(self, steps, tile_rows=0, tile_cols=0):
         """1, or 2 for the two-step LDS-blocked kernel (FP32/16-bit storage);
-        tile 64 x {4, 8, 16} or 128 x {4, 8} (0 = default 64 x 8)."""
+        tile 64 x {4, 8, 16, 32} or 128 x {4, 8} (0 = 64 x 8)."""
         _check(load().smrt_set_steps_per_launch(self._ctx, int(steps), int(tile_cols), int(tile_rows)))
 
     def set_tile_order(self, panel_cols):

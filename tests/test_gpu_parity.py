@@ -351,7 +351,7 @@ def test_convert_between_storage_types(smrt):
 @pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
 @pytest.mark.parametrize("boundary", ["periodic", "cavity"])
 @pytest.mark.parametrize("scheme", ["srt", "smrt", "trt"])
-@pytest.mark.parametrize("tile", [(64, 4), (64, 8), (64, 16), (128, 4), (128, 8)])
+@pytest.mark.parametrize("tile", [(64, 4), (64, 8), (64, 16), (64, 32), (128, 4), (128, 8)])
 def test_two_step_kernel_equals_single_steps(smrt, storage, boundary, scheme, tile):
     """The same per-node arithmetic: bitwise equal to one-step launches, on a
     ragged lattice (tiles cut at both edges) over an odd step count."""
@@ -384,7 +384,7 @@ def test_two_step_kernel_small_cavities(smrt, nx, ny):
 
 
 @pytest.mark.parametrize("boundary", ["periodic", "cavity"])
-@pytest.mark.parametrize("tile", [(64, 8), (128, 4)])
+@pytest.mark.parametrize("tile", [(64, 8), (64, 16), (128, 4)])
 def test_tile_order_does_not_change_results(smrt, boundary, tile):
     """Every tile order (row-major, XCD panels of several widths, ragged last
     panel, a panel wider than the lattice) computes each tile exactly once."""
