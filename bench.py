@@ -298,6 +298,7 @@ def batch_to_steady(args):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     chosen = b.autotune(steps=20)
+    spl_batch = b.steps_per_launch
     tune_steps = b.steps_done
     steps, status, res = b.run(args.tol, args.window, args.max_steps - tune_steps)
     torch.cuda.synchronize()
@@ -319,7 +320,8 @@ def batch_to_steady(args):
         "cavities_per_second": round(args.count / wall, 3),
         "seconds": round(wall, 3),
         "node_updates": updates,
-        "autotuned_launch": {"bx": chosen[0], "by": chosen[1], "grid": chosen[2]},
+        "autotuned_launch": {"bx": chosen[0], "by": chosen[1], "grid": chosen[2],
+                             "steps_per_launch": spl_batch},
         "steady": int((st == smrt.STEADY).sum()), "unstable": int((st == smrt.UNSTABLE).sum()),
         "capped": int((st == smrt.RUNNING).sum()),
         "per_cavity": [{"n": int(a), "re": round(float(r), 2), "steps": int(k),
@@ -473,19 +475,33 @@ def main():
         residuals.append(window(ev[i]))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kernel_ms = sum(a.elapsed_time(b) for a, b in ev) / (args.steps * K)
+    window_ms = sum(a.elapsed_time(b) for a, b in ev) / args.steps
+    kernel_ms = window_ms / K
     mass = solver.mass()
-    steps_per_launch = solver.steps_per_launch
+    spl = solver.steps_per_launch
+    # A window of K steps is q launches of the dominant kernel plus, when spl
+    # does not divide K, one launch of the remaining r steps; that launch is
+    # timed on its own (same stream, HIP events) and taken out.
+    q, r = divmod(K, spl)
+    rem_ms = 0.0
+    if r:
+        reps = 20
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            solver.step(r)  # one launch of r steps each
+        e1.record(stream)
+        torch.cuda.synchronize()
+        rem_ms = e0.elapsed_time(e1) / reps
     solver.close()
 
     cells = n * n
     s = STORAGE_BYTES[args.storage]
     # The dominant kernel reads d(t) and writes d(t + spl) once per node per
     # launch: 9 loads + 9 stores per node whether it advances one time step
-    # (stream_collide) or two through LDS (stream_collide_x2).
-    spl = steps_per_launch
-    kernel_name = "stream_collide_x2" if spl == 2 else "stream_collide"
-    launch_ms = kernel_ms * spl
+    # (stream_collide) or two or three through LDS (stream_collide_x2 / _x3).
+    kernel_name = {1: "stream_collide", 2: "stream_collide_x2", 3: "stream_collide_x3"}[spl]
+    launch_ms = (window_ms - rem_ms) / q
     alg_bytes = 18 * s * cells
     achieved = alg_bytes / (launch_ms / 1e3) / 1e9
     mlups = cells * K * args.steps / wall / 1e6

@@ -443,46 +443,45 @@ constexpr int X2_THREADS = 256;
 template <typename T, int TX, int TY, int NT = X2_THREADS> struct X2Tile {
     using C = typename Storage<T>::C;
     static constexpr int RX = TX + 2, RY = TY + 2;
-    static constexpr int P1 = (RX * RY + NT - 1) / NT; // ring nodes per thread
-    static constexpr int P2 = (TX * TY + NT - 1) / NT; // tile nodes per thread
-    C mid[9][RY][RX];                                                  // step t+1 (LDS)
+    C mid[9][RY][RX]; // step t+1 on the tile plus a one-node ring (LDS)
 };
 
-// Phase 1 in two halves.  x2_load issues the loads of all ring nodes of the
-// thread (up to 9 P1 loads per lane in flight together); x2_collide collides
-// them and writes step t+1 to LDS.  A periodic ring wraps once (nx >= TX + 2,
-// ny >= TY + 2); a cavity ring skips the nodes beyond the walls.
-template <typename T, int TX, int TY, int NT = X2_THREADS> struct X2Ring {
+// The first step of a multi-step launch, in two halves over a region of
+// RX x RY nodes: the tile (X0, Y0, TX x TY) plus a ring of RING nodes.
+// ring_load issues the loads of all the thread's region nodes (up to 9 P
+// loads per lane in flight together); ring_collide collides them and writes
+// the step to LDS.  Periodic regions wrap once; region nodes more than RING -
+// 1 past column nx or row ny feed no output of the tile and are skipped, and
+// every wrapped node takes the edge path (explicit wrap), so interior pulls
+// all have y - 1 >= Y0 - RING - 1, the row the pull bases start at.  Cavity
+// regions skip the nodes beyond the walls.
+template <typename T, int RX, int RY, int NT> struct RingRegs {
     using C = typename Storage<T>::C;
-    static constexpr int P1 = X2Tile<T, TX, TY, NT>::P1;
-    C d[P1][9];
-    bool live[P1];
+    static constexpr int P = (RX * RY + NT - 1) / NT; // region nodes per thread
+    C d[P][9];
+    bool live[P];
 };
 
-template <typename T, int BC, int TX, int TY, int NT = X2_THREADS>
-__device__ __forceinline__ void x2_load(const T* __restrict__ src, const Geom& g, typename Storage<T>::C lid,
-                                        int X0, int Y0, X2Ring<T, TX, TY, NT>& r)
+template <typename T, int BC, int RX, int RY, int NT, int RING>
+__device__ __forceinline__ void ring_load(const T* __restrict__ src, const Geom& g, typename Storage<T>::C lid,
+                                          int X0, int Y0, RingRegs<T, RX, RY, NT>& r)
 {
-    using Tl = X2Tile<T, TX, TY, NT>;
-    const PullBases<T> pb = pull_bases(src, g, Y0 > 1 ? Y0 - 2 : 0);
+    const PullBases<T> pb = pull_bases(src, g, Y0 > RING ? Y0 - RING - 1 : 0);
 #pragma unroll
-    for (int j = 0; j < Tl::P1; ++j) {
+    for (int j = 0; j < RingRegs<T, RX, RY, NT>::P; ++j) {
         const int i = threadIdx.x + j * NT;
-        const int lx = i % Tl::RX, ly = i / Tl::RX;
-        int x = X0 - 1 + lx, y = Y0 - 1 + ly;
+        const int lx = i % RX, ly = i / RX;
+        const int xu = X0 - RING + lx, yu = Y0 - RING + ly;
+        int x = xu, y = yu;
         if constexpr (BC == PERIODIC) {
-            // Ring nodes past column nx or row ny feed no output of the tile;
-            // skipping them leaves only wrapped nodes on the lattice's outer
-            // ring (x or y in {0, n - 1}), which take the edge path, so every
-            // interior pull has y - 1 >= Y0 - 2, the rows its bases start at.
-            r.live[j] = i < Tl::RX * Tl::RY && x <= g.nx && y <= g.ny;
-            x = x < 0 ? x + g.nx : (x >= g.nx ? x - g.nx : x);
-            y = y < 0 ? y + g.ny : (y >= g.ny ? y - g.ny : y);
+            r.live[j] = i < RX * RY && xu <= g.nx + RING - 1 && yu <= g.ny + RING - 1;
+            x = xu < 0 ? xu + g.nx : (xu >= g.nx ? xu - g.nx : xu);
+            y = yu < 0 ? yu + g.ny : (yu >= g.ny ? yu - g.ny : yu);
         } else {
-            r.live[j] = i < Tl::RX * Tl::RY && (unsigned)x < (unsigned)g.nx && (unsigned)y < (unsigned)g.ny;
+            r.live[j] = i < RX * RY && (unsigned)xu < (unsigned)g.nx && (unsigned)yu < (unsigned)g.ny;
         }
         if (r.live[j]) {
-            const bool edge = (x == 0) | (x == g.nx - 1) | (y == 0) | (y == g.ny - 1);
+            const bool edge = (x != xu) | (y != yu) | (x == 0) | (x == g.nx - 1) | (y == 0) | (y == g.ny - 1);
             if (edge)
                 gather_edge<T, BC>(src, g, x, y, r.d[j], lid);
             else
@@ -491,38 +490,54 @@ __device__ __forceinline__ void x2_load(const T* __restrict__ src, const Geom& g
     }
 }
 
-template <typename T, int SCHEME, int TX, int TY, int NT = X2_THREADS>
-__device__ __forceinline__ void x2_collide(const Coef<typename Storage<T>::C>& k, X2Ring<T, TX, TY, NT>& r,
-                                           X2Tile<T, TX, TY, NT>& sh)
+template <typename T, int SCHEME, int RX, int RY, int NT>
+__device__ __forceinline__ void ring_collide(const Coef<typename Storage<T>::C>& k, RingRegs<T, RX, RY, NT>& r,
+                                             typename Storage<T>::C (&m)[9][RY][RX])
 {
-    using Tl = X2Tile<T, TX, TY, NT>;
 #pragma unroll
-    for (int j = 0; j < Tl::P1; ++j) {
+    for (int j = 0; j < RingRegs<T, RX, RY, NT>::P; ++j) {
         if (!r.live[j]) continue;
         const int i = threadIdx.x + j * NT;
-        const int lx = i % Tl::RX, ly = i / Tl::RX;
+        const int lx = i % RX, ly = i / RX;
         collide<SCHEME, T>(r.d[j], k);
         if constexpr (Storage<T>::kRounds) r.d[j][0] = Storage<T>::stored_value(r.d[j][0], 0);
 #pragma unroll
-        for (int a = 0; a < 9; ++a) sh.mid[a][ly][lx] = r.d[j][a];
+        for (int a = 0; a < 9; ++a) m[a][ly][lx] = r.d[j][a];
     }
 }
 
-template <typename T, int SCHEME, int BC, int TX, int TY, int NT = X2_THREADS>
-__device__ __forceinline__ void x2_phase1(const T* __restrict__ src, const Geom& g,
-                                          const Coef<typename Storage<T>::C>& k, int X0, int Y0,
-                                          X2Tile<T, TX, TY, NT>& sh)
+// Pull of node (x, y) of the lattice from a step held in LDS as m[9][RY][RX],
+// the node at local (lx, ly): bounce-back from the node's own opposite
+// population where the source lies beyond a cavity wall (plus the lid term
+// from the lid row).  Periodic regions hold the wrapped nodes' values, so
+// their pulls need no wrap.
+template <typename T, int BC, int RX, int RY>
+__device__ __forceinline__ void pull_lds(const typename Storage<T>::C (&m)[9][RY][RX], const Geom& g,
+                                         typename Storage<T>::C lid, int lx, int ly, int x, int y,
+                                         typename Storage<T>::C d[9])
 {
-    X2Ring<T, TX, TY, NT> r;
-    x2_load<T, BC, TX, TY, NT>(src, g, k.lid, X0, Y0, r);
-    x2_collide<T, SCHEME, TX, TY, NT>(k, r, sh);
+    using C = typename Storage<T>::C;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) d[a] = m[a][ly - EY[a]][lx - EX[a]];
+    if constexpr (BC == CAVITY) {
+        // only lanes on the lattice's outer ring have sources beyond a wall
+        if ((x == 0) | (x == g.nx - 1) | (y == 0) | (y == g.ny - 1)) {
+#pragma unroll
+            for (int a = 1; a < 9; ++a) {
+                const int sx = x - EX[a], sy = y - EY[a];
+                const bool inside = (unsigned)sx < (unsigned)g.nx && (unsigned)sy < (unsigned)g.ny;
+                const C own = m[OPP[a]][ly][lx];
+                d[a] = inside ? d[a] : ((sy == g.ny) ? own + C(EX[a]) * lid : own);
+            }
+        }
+    }
 }
 
-// Phase 2: pull step t+1 from LDS (bounce-back from the node's own opposite
-// population where the source lies beyond a cavity wall), collide, store t+2.
-template <typename T, int SCHEME, int BC, int TX, int TY, int NT = X2_THREADS>
-__device__ __forceinline__ void x2_phase2(T* __restrict__ dst, const Geom& g, const Coef<typename Storage<T>::C>& k,
-                                          int X0, int Y0, const X2Tile<T, TX, TY, NT>& sh)
+// Last step of a multi-step launch: pull the previous step from LDS (held on
+// the tile plus a one-node ring), collide, store to HBM.
+template <typename T, int SCHEME, int BC, int TX, int TY, int NT>
+__device__ __forceinline__ void lds_to_hbm(T* __restrict__ dst, const Geom& g, const Coef<typename Storage<T>::C>& k,
+                                           int X0, int Y0, const typename Storage<T>::C (&m)[9][TY + 2][TX + 2])
 {
     using C = typename Storage<T>::C;
     const StoreBases<T> sb = store_bases(dst, g, Y0);
@@ -530,25 +545,42 @@ __device__ __forceinline__ void x2_phase2(T* __restrict__ dst, const Geom& g, co
         const int tx = i % TX, ty = i / TX;
         const int x = X0 + tx, y = Y0 + ty;
         if (x >= g.nx || y >= g.ny) continue;
-        const int lx = tx + 1, ly = ty + 1;
         C d[9];
-#pragma unroll
-        for (int a = 0; a < 9; ++a) d[a] = sh.mid[a][ly - EY[a]][lx - EX[a]];
-        if constexpr (BC == CAVITY) {
-            // only lanes on the lattice's outer ring have sources beyond a wall
-            if ((x == 0) | (x == g.nx - 1) | (y == 0) | (y == g.ny - 1)) {
-#pragma unroll
-                for (int a = 1; a < 9; ++a) {
-                    const int sx = x - EX[a], sy = y - EY[a];
-                    const bool inside = (unsigned)sx < (unsigned)g.nx && (unsigned)sy < (unsigned)g.ny;
-                    const C own = sh.mid[OPP[a]][ly][lx];
-                    d[a] = inside ? d[a] : ((sy == g.ny) ? own + C(EX[a]) * k.lid : own);
-                }
-            }
-        }
+        pull_lds<T, BC, TX + 2, TY + 2>(m, g, k.lid, tx + 1, ty + 1, x, y, d);
         collide<SCHEME, T>(d, k);
         scatter_store<T>(sb, g, x, y, d);
     }
+}
+
+// Phase 1 of the two-step launch: step t+1 on the tile plus a one-node ring,
+// into LDS.  A periodic lattice needs nx >= TX + 2 and ny >= TY + 2.
+template <typename T, int SCHEME, int BC, int TX, int TY, int NT = X2_THREADS>
+__device__ __forceinline__ void x2_phase1(const T* __restrict__ src, const Geom& g,
+                                          const Coef<typename Storage<T>::C>& k, int X0, int Y0,
+                                          X2Tile<T, TX, TY, NT>& sh)
+{
+    RingRegs<T, TX + 2, TY + 2, NT> r;
+    ring_load<T, BC, TX + 2, TY + 2, NT, 1>(src, g, k.lid, X0, Y0, r);
+    ring_collide<T, SCHEME, TX + 2, TY + 2, NT>(k, r, sh.mid);
+}
+
+// Phase 2 of the two-step launch: pull step t+1 from LDS, collide, store t+2.
+template <typename T, int SCHEME, int BC, int TX, int TY, int NT = X2_THREADS>
+__device__ __forceinline__ void x2_phase2(T* __restrict__ dst, const Geom& g, const Coef<typename Storage<T>::C>& k,
+                                          int X0, int Y0, const X2Tile<T, TX, TY, NT>& sh)
+{
+    lds_to_hbm<T, SCHEME, BC, TX, TY, NT>(dst, g, k, X0, Y0, sh.mid);
+}
+
+// Tile of this workgroup (row-major or XCD panel order).
+__device__ __forceinline__ void workgroup_tile(const Geom& g, int TX, int TY, int& X0, int& Y0)
+{
+    const int tiles_y = (int)gridDim.x / g.tiles_x;
+    const int pos = g.panel > 0 ? xcd_contiguous(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    int tx, ty;
+    panel_tile(pos, g.tiles_x, tiles_y, g.panel, tx, ty);
+    X0 = tx * TX;
+    Y0 = ty * TY;
 }
 
 template <typename T, int SCHEME, int BC, int TX, int TY, int NT>
@@ -556,14 +588,80 @@ __global__ void __launch_bounds__(NT) stream_collide_x2(const T* __restrict__ sr
                                                         Coef<typename Storage<T>::C> k)
 {
     __shared__ X2Tile<T, TX, TY, NT> sh;
-    const int tiles_y = (int)gridDim.x / g.tiles_x;
-    const int pos = g.panel > 0 ? xcd_contiguous(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    int tx, ty;
-    panel_tile(pos, g.tiles_x, tiles_y, g.panel, tx, ty);
-    const int X0 = tx * TX, Y0 = ty * TY;
+    int X0, Y0;
+    workgroup_tile(g, TX, TY, X0, Y0);
     x2_phase1<T, SCHEME, BC, TX, TY, NT>(src, g, k, X0, Y0, sh);
     __syncthreads();
     x2_phase2<T, SCHEME, BC, TX, TY, NT>(dst, g, k, X0, Y0, sh);
+}
+
+// Three time steps per launch.  Step t+1 on the tile plus a two-node ring
+// goes to LDS (a); step t+2 on the tile plus a one-node ring is pulled from
+// it, collided into registers and, after a barrier, written over the same
+// LDS (b); step t+3 is pulled from b and stored.  HBM traffic per
+// node-update falls to a third of a one-step launch; the rings add
+// ((TX+4)(TY+4) + (TX+2)(TY+2)) / (TX TY) - 2 redundant collisions.  Same
+// per-node arithmetic, so the results are bitwise those of three one-step
+// launches.  A periodic lattice needs nx >= TX + 4 and ny >= TY + 4.
+template <typename T, int TX, int TY> struct X3Tile {
+    using C = typename Storage<T>::C;
+    union {
+        C a[9][TY + 4][TX + 4]; // step t+1
+        C b[9][TY + 2][TX + 2]; // step t+2, written over a
+    };
+};
+
+template <typename T, int SCHEME, int BC, int TX, int TY, int NT>
+__device__ __forceinline__ void x3_tile(const T* __restrict__ src, T* __restrict__ dst, const Geom& g,
+                                        const Coef<typename Storage<T>::C>& k, int X0, int Y0, X3Tile<T, TX, TY>& sh)
+{
+    using C = typename Storage<T>::C;
+    constexpr int AX = TX + 4, AY = TY + 4, BX = TX + 2, BY = TY + 2;
+    constexpr int P2 = (BX * BY + NT - 1) / NT;
+    {
+        RingRegs<T, AX, AY, NT> r;
+        ring_load<T, BC, AX, AY, NT, 2>(src, g, k.lid, X0, Y0, r);
+        ring_collide<T, SCHEME, AX, AY, NT>(k, r, sh.a);
+    }
+    __syncthreads();
+    C d[P2][9];
+    bool live[P2];
+#pragma unroll
+    for (int j = 0; j < P2; ++j) {
+        const int i = threadIdx.x + j * NT;
+        const int lx = i % BX, ly = i / BX;
+        const int x = X0 - 1 + lx, y = Y0 - 1 + ly; // unwrapped
+        if constexpr (BC == PERIODIC)
+            live[j] = i < BX * BY && x <= g.nx && y <= g.ny;
+        else
+            live[j] = i < BX * BY && (unsigned)x < (unsigned)g.nx && (unsigned)y < (unsigned)g.ny;
+        if (live[j]) {
+            pull_lds<T, BC, AX, AY>(sh.a, g, k.lid, lx + 1, ly + 1, x, y, d[j]);
+            collide<SCHEME, T>(d[j], k);
+            if constexpr (Storage<T>::kRounds) d[j][0] = Storage<T>::stored_value(d[j][0], 0);
+        }
+    }
+    __syncthreads(); // every pull from a is done before b overwrites it
+#pragma unroll
+    for (int j = 0; j < P2; ++j) {
+        if (!live[j]) continue;
+        const int i = threadIdx.x + j * NT;
+        const int lx = i % BX, ly = i / BX;
+#pragma unroll
+        for (int a = 0; a < 9; ++a) sh.b[a][ly][lx] = d[j][a];
+    }
+    __syncthreads();
+    lds_to_hbm<T, SCHEME, BC, TX, TY, NT>(dst, g, k, X0, Y0, sh.b);
+}
+
+template <typename T, int SCHEME, int BC, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT) stream_collide_x3(const T* __restrict__ src, T* __restrict__ dst, Geom g,
+                                                        Coef<typename Storage<T>::C> k)
+{
+    __shared__ X3Tile<T, TX, TY> sh;
+    int X0, Y0;
+    workgroup_tile(g, TX, TY, X0, Y0);
+    x3_tile<T, SCHEME, BC, TX, TY, NT>(src, dst, g, k, X0, Y0, sh);
 }
 
 // ---------------------------------------------------------------------------

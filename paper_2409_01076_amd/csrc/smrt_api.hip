@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <type_traits>
 #include <limits>
 #include <new>
 #include <string>
@@ -197,7 +198,7 @@ struct smrt_ctx {
     int cur = 0;                   // 0: state in buffer A, 1: in buffer B
     int64_t steps = 0, snap_step = 0;
     int bx = 256, by = 1, rows = 1;
-    int fused = 1;                 // time steps per launch (1, or 2 with the LDS-blocked kernel)
+    int fused = 1;                 // time steps per launch (1, or 2 / 3 with the LDS-blocked kernels)
     int fused_cols = 64, fused_rows = 8; // tile of the two-step kernel
     int panel = 0;                 // two-step kernel: tile order (0 = row-major)
 
@@ -276,7 +277,17 @@ int launch_x2(smrt_ctx* c, const T* s, T* d, const smrt::Geom& g, const smrt::Co
     return SMRT_OK;
 }
 
-template <typename T, int TX, int TY> int launch_step2_tile(smrt_ctx* c, const void* src, void* dst)
+template <typename T, int SCHEME, int BC, int TX, int TY>
+int launch_x3(smrt_ctx* c, const T* s, T* d, const smrt::Geom& g, const smrt::Coef<typename smrt::Storage<T>::C>& k,
+              int ntiles)
+{
+    constexpr int NT = x2_threads(TX, TY);
+    smrt::stream_collide_x3<T, SCHEME, BC, TX, TY, NT><<<ntiles, NT, 0, c->stream>>>(s, d, g, k);
+    return SMRT_OK;
+}
+
+// One launch of the two-step (STEPS = 2) or three-step (STEPS = 3) kernel.
+template <typename T, int STEPS, int TX, int TY> int launch_multi_tile(smrt_ctx* c, const void* src, void* dst)
 {
     using C = typename smrt::Storage<T>::C;
     smrt::Geom g = c->geom();
@@ -297,16 +308,20 @@ template <typename T, int TX, int TY> int launch_step2_tile(smrt_ctx* c, const v
     const T* s = static_cast<const T*>(src);
     T* d = static_cast<T*>(dst);
     const bool per = c->p.boundary == SMRT_PERIODIC;
+    auto go = [&](auto scheme_tag, auto bc_tag) {
+        constexpr int SCHEME = decltype(scheme_tag)::value, BC = decltype(bc_tag)::value;
+        if constexpr (STEPS == 3) return launch_x3<T, SCHEME, BC, TX, TY>(c, s, d, g, k, n);
+        else return launch_x2<T, SCHEME, BC, TX, TY>(c, s, d, g, k, n);
+    };
+    using PER = std::integral_constant<int, smrt::PERIODIC>;
+    using CAV = std::integral_constant<int, smrt::CAVITY>;
     switch (c->p.scheme) {
     case SMRT_SCHEME_SRT:
-        return per ? launch_x2<T, smrt::SRT, smrt::PERIODIC, TX, TY>(c, s, d, g, k, n)
-                   : launch_x2<T, smrt::SRT, smrt::CAVITY, TX, TY>(c, s, d, g, k, n);
+        return per ? go(std::integral_constant<int, smrt::SRT>{}, PER{}) : go(std::integral_constant<int, smrt::SRT>{}, CAV{});
     case SMRT_SCHEME_SMRT:
-        return per ? launch_x2<T, smrt::SMRT, smrt::PERIODIC, TX, TY>(c, s, d, g, k, n)
-                   : launch_x2<T, smrt::SMRT, smrt::CAVITY, TX, TY>(c, s, d, g, k, n);
+        return per ? go(std::integral_constant<int, smrt::SMRT>{}, PER{}) : go(std::integral_constant<int, smrt::SMRT>{}, CAV{});
     default:
-        return per ? launch_x2<T, smrt::TRT, smrt::PERIODIC, TX, TY>(c, s, d, g, k, n)
-                   : launch_x2<T, smrt::TRT, smrt::CAVITY, TX, TY>(c, s, d, g, k, n);
+        return per ? go(std::integral_constant<int, smrt::TRT>{}, PER{}) : go(std::integral_constant<int, smrt::TRT>{}, CAV{});
     }
 }
 
@@ -314,13 +329,31 @@ template <typename T, int TX, int TY> int launch_step2_tile(smrt_ctx* c, const v
 template <typename T> int launch_step2(smrt_ctx* c, const void* src, void* dst)
 {
     if (c->fused_cols == 128) {
-        if (c->fused_rows == 4) return launch_step2_tile<T, 128, 4>(c, src, dst);
-        return launch_step2_tile<T, 128, 8>(c, src, dst);
+        if (c->fused_rows == 4) return launch_multi_tile<T, 2, 128, 4>(c, src, dst);
+        return launch_multi_tile<T, 2, 128, 8>(c, src, dst);
     }
-    if (c->fused_rows == 4) return launch_step2_tile<T, 64, 4>(c, src, dst);
-    if (c->fused_rows == 16) return launch_step2_tile<T, 64, 16>(c, src, dst);
-    if (c->fused_rows == 32) return launch_step2_tile<T, 64, 32>(c, src, dst);
-    return launch_step2_tile<T, 64, 8>(c, src, dst);
+    if (c->fused_rows == 4) return launch_multi_tile<T, 2, 64, 4>(c, src, dst);
+    if (c->fused_rows == 16) return launch_multi_tile<T, 2, 64, 16>(c, src, dst);
+    if (c->fused_rows == 32) return launch_multi_tile<T, 2, 64, 32>(c, src, dst);
+    return launch_multi_tile<T, 2, 64, 8>(c, src, dst);
+}
+
+// Three-step tiles offered: 64 x {8, 16}.
+template <typename T> int launch_step3(smrt_ctx* c, const void* src, void* dst)
+{
+    if (c->fused_rows == 16) return launch_multi_tile<T, 3, 64, 16>(c, src, dst);
+    return launch_multi_tile<T, 3, 64, 8>(c, src, dst);
+}
+
+// Three time steps in one launch (FP32 and 16-bit storage only).
+int dispatch_step3(smrt_ctx* c, const void* src, void* dst)
+{
+    switch (c->p.storage) {
+    case SMRT_F32: return launch_step3<float>(c, src, dst);
+    case SMRT_F16: return launch_step3<_Float16>(c, src, dst);
+    case SMRT_BF16: return launch_step3<smrt::bf16>(c, src, dst);
+    default: return fail(SMRT_EINVAL, "three-step launches need FP32 or 16-bit storage");
+    }
 }
 
 // Two time steps in one launch (FP32 and 16-bit storage only).
@@ -437,25 +470,24 @@ int smrt_create(const smrt_params* p, void* dev_ws, size_t ws_bytes, smrt_ctx** 
         c->L = L;
         // Default block shape: one row segment per block, as wide as the
         // lattice allows (512 measured best on 4096^2, within 1-2% of 256).
-        // Two steps per launch wherever the LDS-blocked kernel applies (FP32
-        // and 16-bit storage; periodic lattices at least a tile plus its
-        // ring).  Tile, measured on 1024^2 .. 4096^2: 64 x 16 (512 threads)
-        // while that still gives >= 4096 workgroups, else 64 x 32 (512
-        // threads) while that gives >= 512, else 64 x 4; tiles in XCD panels
-        // of 8 tile columns (FP32 reads drop from 1.67x to 1.08x the
-        // algorithmic bytes).
+        // FP32 and 16-bit storage take the LDS-blocked kernels, tiles in XCD
+        // panels of 8 tile columns.  Measured on 512^2 .. 4096^2: three steps
+        // per launch with 64 x 16 tiles (512 threads) while that gives >= 1024
+        // workgroups; else two steps with 64 x 32 tiles while that gives >=
+        // 512, else with 64 x 4.  Periodic lattices need room for the rings.
         if (p->storage != SMRT_F64) {
             const int64_t cols = (p->nx + 63) / 64;
+            const bool per = p->boundary == SMRT_PERIODIC;
             c->fused_cols = 64;
-            if (cols * ((p->ny + 15) / 16) >= 4096)
-                c->fused_rows = 16;
-            else if (cols * ((p->ny + 31) / 32) >= 512)
-                c->fused_rows = 32;
-            else
-                c->fused_rows = 4;
-            if (p->boundary == SMRT_PERIODIC && p->ny < c->fused_rows + 2) c->fused_rows = 4;
-            if (p->boundary == SMRT_CAVITY || (p->nx >= 66 && p->ny >= c->fused_rows + 2)) c->fused = 2;
             c->panel = 8;
+            if (cols * ((p->ny + 15) / 16) >= 1024 && (!per || (p->nx >= 68 && p->ny >= 20))) {
+                c->fused = 3;
+                c->fused_rows = 16;
+            } else {
+                c->fused_rows = cols * ((p->ny + 31) / 32) >= 512 ? 32 : 4;
+                if (per && p->ny < c->fused_rows + 2) c->fused_rows = 4;
+                if (!per || (p->nx >= 66 && p->ny >= c->fused_rows + 2)) c->fused = 2;
+            }
         }
         if (p->nx >= 512) {
             c->bx = 512; c->by = 1;
@@ -548,13 +580,16 @@ int smrt_step(smrt_ctx* c, int64_t n)
     if (n < 0) return fail(SMRT_EINVAL, "step count must be >= 0 (got %lld)", (long long)n);
     int64_t left = n;
     while (left > 0) {
-        const bool two = c->fused == 2 && left >= 2;
-        int rc = two ? dispatch_step2(c, c->buffer(c->cur), c->buffer(c->cur ^ 1))
-                     : dispatch_step(c, c->buffer(c->cur), c->buffer(c->cur ^ 1));
+        // the largest launch that fits: fused steps, then 2 (the three-step
+        // tiles are also two-step tiles), then 1
+        const int k = (int)std::min<int64_t>(c->fused, left);
+        const void* src = c->buffer(c->cur);
+        void* dst = c->buffer(c->cur ^ 1);
+        int rc = k == 3 ? dispatch_step3(c, src, dst) : k == 2 ? dispatch_step2(c, src, dst) : dispatch_step(c, src, dst);
         if (rc) return rc;
         c->cur ^= 1;
-        c->steps += two ? 2 : 1;
-        left -= two ? 2 : 1;
+        c->steps += k;
+        left -= k;
     }
     return n ? after_launch("stream_collide") : SMRT_OK;
 }
@@ -633,18 +668,21 @@ int smrt_set_launch(smrt_ctx* c, int32_t bx, int32_t by, int32_t rows)
 int smrt_set_steps_per_launch(smrt_ctx* c, int32_t steps, int32_t tile_cols, int32_t tile_rows)
 {
     if (!c) return fail(SMRT_EINVAL, "context is NULL");
-    if (steps != 1 && steps != 2) return fail(SMRT_EINVAL, "steps per launch must be 1 or 2 (got %d)", steps);
+    if (steps < 1 || steps > 3) return fail(SMRT_EINVAL, "steps per launch must be 1, 2 or 3 (got %d)", steps);
     if (tile_cols == 0) tile_cols = 64;
-    if (tile_rows == 0) tile_rows = 8;
-    const bool ok = (tile_cols == 64 && (tile_rows == 4 || tile_rows == 8 || tile_rows == 16 || tile_rows == 32)) ||
-                    (tile_cols == 128 && (tile_rows == 4 || tile_rows == 8));
-    if (!ok) return fail(SMRT_EINVAL, "two-step tile %d x %d not offered", tile_cols, tile_rows);
-    if (steps == 2) {
-        if (c->p.storage == SMRT_F64) return fail(SMRT_EINVAL, "two-step launches need FP32 or 16-bit storage");
-        // A periodic ring wraps once, which needs the lattice wider than the tile.
-        if (c->p.boundary == SMRT_PERIODIC && (c->p.nx < tile_cols + 2 || c->p.ny < tile_rows + 2))
-            return fail(SMRT_EINVAL, "periodic two-step launches need nx >= %d and ny >= %d", tile_cols + 2,
-                        tile_rows + 2);
+    if (tile_rows == 0) tile_rows = steps == 3 ? 16 : 8;
+    const bool ok = steps == 3 ? tile_cols == 64 && (tile_rows == 8 || tile_rows == 16)
+                               : (tile_cols == 64 && (tile_rows == 4 || tile_rows == 8 || tile_rows == 16 ||
+                                                      tile_rows == 32)) ||
+                                     (tile_cols == 128 && (tile_rows == 4 || tile_rows == 8));
+    if (!ok) return fail(SMRT_EINVAL, "%d-step tile %d x %d not offered", steps, tile_cols, tile_rows);
+    if (steps >= 2) {
+        if (c->p.storage == SMRT_F64) return fail(SMRT_EINVAL, "multi-step launches need FP32 or 16-bit storage");
+        // A periodic ring wraps once, which needs the lattice wider than the tile plus its rings.
+        const int ring = steps - 1;
+        if (c->p.boundary == SMRT_PERIODIC && (c->p.nx < tile_cols + 2 * ring || c->p.ny < tile_rows + 2 * ring))
+            return fail(SMRT_EINVAL, "periodic %d-step launches need nx >= %d and ny >= %d", steps,
+                        tile_cols + 2 * ring, tile_rows + 2 * ring);
     }
     c->fused = steps;
     c->fused_cols = tile_cols;

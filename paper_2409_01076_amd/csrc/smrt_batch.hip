@@ -154,7 +154,7 @@ struct smrt_batch {
     bool owns_ws = false;
     double* host_result = nullptr;  // pinned, count * RED_VALUES
     smrt::BatchLaunch shape{64, 4};
-    bool two = false;               // two time steps per launch (LDS-blocked kernel)
+    int multi = 1;                  // time steps per launch (2 and 3: the LDS-blocked kernels)
     int grid = 0;                   // workgroups per step launch
     int parity = 0;                 // buffer holding the running cavities' state
     int64_t steps = 0, snap_step = 0;
@@ -229,10 +229,25 @@ void launch_two_tile(smrt_batch* b, hipStream_t s, int parity, dim3 grid)
         b->desc(), b->table(), b->ntiles_dev(), reinterpret_cast<T*>(b->state()), parity);
 }
 
-template <typename T, int SCHEME> void launch_typed_scheme(smrt_batch* b, hipStream_t s, int parity, bool two)
+template <typename T, int SCHEME, int TY>
+void launch_three_tile(smrt_batch* b, hipStream_t s, int parity, dim3 grid)
+{
+    constexpr int NT = two_threads(TY);
+    smrt::batch_stream_collide_x3<T, SCHEME, 64, TY, NT><<<grid, NT, 0, s>>>(
+        b->desc(), b->table(), b->ntiles_dev(), reinterpret_cast<T*>(b->state()), parity);
+}
+
+// One launch of k time steps (k = 2, 3: 64 x shape.by tiles; the tile table
+// is built for that shape, so a shorter remainder launch uses the same table).
+template <typename T, int SCHEME> void launch_typed_scheme(smrt_batch* b, hipStream_t s, int parity, int k)
 {
     dim3 grid((unsigned)std::max(b->grid, 1));
-    if (two) {
+    if (k == 3) {
+        if (b->shape.by == 16) launch_three_tile<T, SCHEME, 16>(b, s, parity, grid);
+        else launch_three_tile<T, SCHEME, 8>(b, s, parity, grid);
+        return;
+    }
+    if (k == 2) {
         if (b->shape.by == 16) launch_two_tile<T, SCHEME, 16>(b, s, parity, grid);
         else if (b->shape.by == 8) launch_two_tile<T, SCHEME, 8>(b, s, parity, grid);
         else launch_two_tile<T, SCHEME, 4>(b, s, parity, grid);
@@ -243,33 +258,36 @@ template <typename T, int SCHEME> void launch_typed_scheme(smrt_batch* b, hipStr
                                                                 reinterpret_cast<T*>(b->state()), parity, b->shape);
 }
 
-template <typename T> void launch_step_typed(smrt_batch* b, hipStream_t s, int parity, bool two)
+template <typename T> void launch_step_typed(smrt_batch* b, hipStream_t s, int parity, int k)
 {
     switch (b->p.scheme) {
-    case SMRT_SCHEME_SRT: launch_typed_scheme<T, smrt::SRT>(b, s, parity, two); break;
-    case SMRT_SCHEME_SMRT: launch_typed_scheme<T, smrt::SMRT>(b, s, parity, two); break;
-    default: launch_typed_scheme<T, smrt::TRT>(b, s, parity, two); break;
+    case SMRT_SCHEME_SRT: launch_typed_scheme<T, smrt::SRT>(b, s, parity, k); break;
+    case SMRT_SCHEME_SMRT: launch_typed_scheme<T, smrt::SMRT>(b, s, parity, k); break;
+    default: launch_typed_scheme<T, smrt::TRT>(b, s, parity, k); break;
     }
 }
 
-// One launch: one time step, or two when `two` (FP64 storage has no
-// two-step kernel).
-void launch_step(smrt_batch* b, hipStream_t s, int parity, bool two)
+// One launch of k = 1, 2 or 3 time steps (FP64 storage has only the
+// one-step kernel).
+void launch_step(smrt_batch* b, hipStream_t s, int parity, int k)
 {
     switch (b->p.storage) {
-    case SMRT_F64: launch_step_typed<double>(b, s, parity, false); break;
-    case SMRT_F32: launch_step_typed<float>(b, s, parity, two); break;
-    case SMRT_F16: launch_step_typed<_Float16>(b, s, parity, two); break;
-    default: launch_step_typed<smrt::bf16>(b, s, parity, two); break;
+    case SMRT_F64: launch_step_typed<double>(b, s, parity, 1); break;
+    case SMRT_F32: launch_step_typed<float>(b, s, parity, k); break;
+    case SMRT_F16: launch_step_typed<_Float16>(b, s, parity, k); break;
+    default: launch_step_typed<smrt::bf16>(b, s, parity, k); break;
     }
 }
 
-// Captures kGraphSteps launches (of one or two steps each, by the current
-// mode) starting from `parity` on the private stream and instantiates them.
+// Time steps per launch in the current mode (FP64: always 1).
+int multi_steps(const smrt_batch* b) { return b->p.storage == SMRT_F64 ? 1 : b->multi; }
+
+// Captures kGraphSteps launches (of multi_steps(b) steps each) starting from
+// `parity` on the private stream and instantiates them.
 int capture_graph(smrt_batch* b, int parity)
 {
     HIP_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < kGraphSteps; ++i) launch_step(b, b->capture, parity ^ (i & 1), b->two);
+    for (int i = 0; i < kGraphSteps; ++i) launch_step(b, b->capture, parity ^ (i & 1), multi_steps(b));
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(b->capture, &g);
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
@@ -284,12 +302,10 @@ int capture_graph(smrt_batch* b, int parity)
     return SMRT_OK;
 }
 
-bool two_step_mode(const smrt_batch* b) { return b->two && b->p.storage != SMRT_F64; }
-
 int enqueue_steps(smrt_batch* b, int64_t n)
 {
     if (b->ntiles == 0 || n <= 0) return SMRT_OK;
-    const int unit = two_step_mode(b) ? 2 : 1;
+    const int unit = multi_steps(b);
     const int64_t per_graph = (int64_t)kGraphSteps * unit;
     while (n > 0) {
         if (n >= per_graph) {
@@ -301,13 +317,13 @@ int enqueue_steps(smrt_batch* b, int64_t n)
             n -= per_graph;
             b->steps += per_graph;
         } else {
-            const bool two = unit == 2 && n >= 2;
-            launch_step(b, b->stream, b->parity, two);
+            const int k = (int)std::min<int64_t>(unit, n);
+            launch_step(b, b->stream, b->parity, k);
             int rc = after_launch("batch_stream_collide");
             if (rc) return rc;
             b->parity ^= 1;
-            n -= two ? 2 : 1;
-            b->steps += two ? 2 : 1;
+            n -= k;
+            b->steps += k;
         }
     }
     return SMRT_OK;
@@ -438,10 +454,11 @@ int smrt_batch_create(const smrt_batch_params* p, void* dev_ws, size_t ws_bytes,
             smrt_batch_destroy(b);
             return hip_fail(e, "hipMemsetAsync");
         }
-        // Default launch: 64 x 4 tiles, one pass over the table per launch,
-        // two time steps per launch except for FP64 storage.
-        b->shape = kShapes[0];
-        b->two = p->storage != SMRT_F64;
+        // Default launch: one pass over the table per launch; FP64 one step
+        // per launch with 64 x 4 tiles, other storage three steps with 64 x 16
+        // tiles (the fastest on every batch of 16..256 cavities measured).
+        b->shape = p->storage == SMRT_F64 ? kShapes[0] : smrt::BatchLaunch{64, 16};
+        b->multi = p->storage == SMRT_F64 ? 1 : 3;
         int total_tiles = 0;
         for (const auto& c : b->plan.desc) total_tiles += tiles_of(c.nx, c.ny, b->shape);
         b->grid = total_tiles;
@@ -539,30 +556,32 @@ int smrt_batch_autotune(smrt_batch* b, int32_t steps, int32_t* chosen)
     float best = std::numeric_limits<float>::infinity();
     smrt::BatchLaunch best_shape = b->shape;
     int best_grid = b->grid;
-    bool best_two = b->two;
+    int best_multi = b->multi;
     int rc = SMRT_OK;
     // Candidates: every one-step shape, then (except for FP64) the two-step
-    // kernel with 64 x 4, 64 x 8 and 64 x 16 tiles; times are per time step.
-    static const int kTwoRows[] = {4, 8, 16};
-    const int n_two = b->p.storage == SMRT_F64 ? 0 : 3;
-    for (int s = 0; s < kNumShapes + n_two && rc == SMRT_OK; ++s) {
-        const bool two = s >= kNumShapes;
-        b->shape = two ? smrt::BatchLaunch{64, kTwoRows[s - kNumShapes]} : kShapes[s];
-        b->two = two;
+    // kernel with 64 x 4, 64 x 8 and 64 x 16 tiles and the three-step kernel
+    // with 64 x 8 and 64 x 16 tiles; times are per time step.
+    static const int kMultiSteps[] = {2, 2, 2, 3, 3};
+    static const int kMultiRows[] = {4, 8, 16, 8, 16};
+    const int n_multi = b->p.storage == SMRT_F64 ? 0 : 5;
+    for (int s = 0; s < kNumShapes + n_multi && rc == SMRT_OK; ++s) {
+        const int multi = s >= kNumShapes ? kMultiSteps[s - kNumShapes] : 1;
+        b->shape = multi > 1 ? smrt::BatchLaunch{64, kMultiRows[s - kNumShapes]} : kShapes[s];
+        b->multi = multi;
         rc = upload_tables(b);
         if (rc) break;
-        const int per_block_waves = two ? two_threads(b->shape.by) / 64 : (b->shape.bx * b->shape.by) / 64;
+        const int per_block_waves = multi > 1 ? two_threads(b->shape.by) / 64 : (b->shape.bx * b->shape.by) / 64;
         const int grids[] = {b->ntiles, cus * std::max(1, 8 / per_block_waves), cus * std::max(1, 16 / per_block_waves),
                              cus * std::max(1, 32 / per_block_waves)};
         for (int gi = 0; gi < 4; ++gi) {
             b->grid = std::min(grids[gi], b->ntiles);
             if (gi > 0 && grids[gi] >= b->ntiles) continue; // same as the full grid
-            const int unit = two ? 2 : 1;
+            const int unit = multi;
             const int launches = std::max(2, steps / unit) & ~1; // even: parity kept
-            launch_step(b, b->stream, b->parity, two); // warm-up pair
-            launch_step(b, b->stream, b->parity ^ 1, two);
+            launch_step(b, b->stream, b->parity, unit); // warm-up pair
+            launch_step(b, b->stream, b->parity ^ 1, unit);
             HIP_TRY(hipEventRecord(e0, b->stream));
-            for (int k = 0; k < launches; ++k) launch_step(b, b->stream, b->parity ^ (k & 1), two);
+            for (int k = 0; k < launches; ++k) launch_step(b, b->stream, b->parity ^ (k & 1), unit);
             HIP_TRY(hipEventRecord(e1, b->stream));
             rc = after_launch("batch autotune");
             if (rc) break;
@@ -575,7 +594,7 @@ int smrt_batch_autotune(smrt_batch* b, int32_t steps, int32_t* chosen)
                 best = per_step;
                 best_shape = b->shape;
                 best_grid = b->grid;
-                best_two = two;
+                best_multi = multi;
             }
         }
     }
@@ -583,7 +602,7 @@ int smrt_batch_autotune(smrt_batch* b, int32_t steps, int32_t* chosen)
     (void)hipEventDestroy(e1);
     if (rc) return rc;
     b->shape = best_shape;
-    b->two = best_two;
+    b->multi = best_multi;
     rc = upload_tables(b);
     if (rc) return rc;
     b->grid = std::min(best_grid, b->ntiles);
@@ -659,5 +678,7 @@ void smrt_batch_destroy(smrt_batch* b)
     if (b->owns_ws && b->ws) (void)hipFree(b->ws);
     delete b;
 }
+
+int32_t smrt_batch_steps_per_launch(const smrt_batch* b) { return b ? multi_steps(b) : -1; }
 
 } // extern "C"

@@ -28,7 +28,7 @@ EXPORTED = (
     "smrt_last_error", "smrt_copy_kernel",
     "smrt_batch_workspace_bytes", "smrt_batch_create", "smrt_batch_step", "smrt_batch_run",
     "smrt_batch_autotune", "smrt_batch_moments", "smrt_batch_init_fields", "smrt_batch_steps_done",
-    "smrt_batch_running", "smrt_batch_destroy",
+    "smrt_batch_running", "smrt_batch_steps_per_launch", "smrt_batch_destroy",
     "smrt_mlp_param_count", "smrt_mlp_workspace_bytes", "smrt_mlp_create", "smrt_mlp_set_params",
     "smrt_mlp_get_params", "smrt_mlp_forward", "smrt_mlp_gradient", "smrt_mlp_train_step",
     "smrt_mlp_destroy", "smrt_gemm_bf16",
@@ -125,6 +125,7 @@ def load():
         "smrt_batch_init_fields": (ctypes.c_int, [vp, i32, vp, vp, vp, i32]),
         "smrt_batch_steps_done": (i64, [vp]),
         "smrt_batch_running": (i32, [vp]),
+        "smrt_batch_steps_per_launch": (i32, [vp]),
         "smrt_batch_destroy": (None, [vp]),
         "smrt_mlp_param_count": (ctypes.c_size_t, [ctypes.POINTER(MlpParams)]),
         "smrt_mlp_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(MlpParams)]),
@@ -336,8 +337,9 @@ class Solver:
         _check(load().smrt_set_launch(self._ctx, int(bx), int(by), int(rows)))
 
     def set_steps_per_launch(self, steps, tile_rows=0, tile_cols=0):
-        """1, or 2 for the two-step LDS-blocked kernel (FP32/16-bit storage);
-        tile 64 x {4, 8, 16, 32} or 128 x {4, 8} (0 = 64 x 8)."""
+        """1, or 2 / 3 for the LDS-blocked kernels (FP32/16-bit storage);
+        two-step tiles 64 x {4, 8, 16, 32} or 128 x {4, 8} (0 = 64 x 8),
+        three-step tiles 64 x {8, 16} (0 = 64 x 16)."""
         _check(load().smrt_set_steps_per_launch(self._ctx, int(steps), int(tile_cols), int(tile_rows)))
 
     def set_tile_order(self, panel_cols):
@@ -437,8 +439,13 @@ class Batch:
                                      status, res))
         return list(steps), list(status), list(res)
 
+    @property
+    def steps_per_launch(self):
+        return int(load().smrt_batch_steps_per_launch(self._ctx))
+
     def autotune(self, steps=20):
-        """Times the candidate launch shapes; returns the chosen (bx, by, grid)."""
+        """Times the candidate launch shapes; returns the chosen (bx, by, grid)
+        (steps_per_launch tells the chosen kernel's steps per launch)."""
         chosen = (ctypes.c_int32 * 3)()
         _check(load().smrt_batch_autotune(self._ctx, int(steps), chosen))
         return tuple(chosen)

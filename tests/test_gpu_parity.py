@@ -403,6 +403,70 @@ def test_tile_order_does_not_change_results(smrt, boundary, tile):
         assert np.array_equal(outs[0], o)
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("boundary", ["periodic", "cavity"])
+@pytest.mark.parametrize("scheme", ["srt", "smrt", "trt"])
+@pytest.mark.parametrize("tile", [(64, 8), (64, 16)])
+def test_three_step_kernel_equals_single_steps(smrt, storage, boundary, scheme, tile):
+    """Three steps per launch (two LDS rings, the middle step written over
+    the first): bitwise equal to one-step launches on a ragged lattice, over
+    step counts that end with a two-step and with a one-step launch."""
+    nx, ny = 203, 77
+    f0 = inputs.perturbed_populations(nx, ny, eps=0.03, seed=7)
+    u = 0.1 if boundary == "cavity" else 0.0
+    for steps in (41, 43):
+        outs = []
+        for spl in (1, 3):
+            with smrt.Solver(nx, ny, scheme=scheme, boundary=boundary, storage=storage, tau=0.56,
+                             u_lid=u, tau_s=0.9) as s:
+                s.set_populations(to_dev(f0, torch.float64))
+                s.set_steps_per_launch(spl, tile_rows=tile[1], tile_cols=tile[0])
+                s.step(steps)
+                assert s.steps_done == steps
+                outs.append(s.populations(torch.float64).cpu().numpy())
+        assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("nx,ny", [(3, 3), (5, 70), (13, 21), (64, 64), (65, 9)])
+def test_three_step_kernel_small_cavities(smrt, nx, ny):
+    outs = []
+    for spl in (1, 3):
+        with smrt.Solver(nx, ny, scheme="smrt", boundary="cavity", storage="f32", tau=0.6,
+                         u_lid=0.1) as s:
+            s.set_steps_per_launch(spl, tile_rows=8)
+            s.step(31)
+            outs.append(s.populations(torch.float64).cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("boundary", ["periodic", "cavity"])
+def test_three_step_tile_order_does_not_change_results(smrt, boundary):
+    nx, ny, steps = 203, 77, 21
+    f0 = inputs.perturbed_populations(nx, ny, eps=0.03, seed=8)
+    outs = []
+    for panel in (0, 1, 3, 8, 1000):
+        with smrt.Solver(nx, ny, scheme="smrt", boundary=boundary, storage="f32", tau=0.56,
+                         u_lid=0.1 if boundary == "cavity" else 0.0) as s:
+            s.set_populations(to_dev(f0, torch.float64))
+            s.set_steps_per_launch(3, tile_rows=16, tile_cols=64)
+            s.set_tile_order(panel)
+            s.step(steps)
+            outs.append(s.populations(torch.float64).cpu().numpy())
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
+
+
+def test_three_step_kernel_rejects_unsupported(smrt):
+    with smrt.Solver(67, 100, scheme="smrt", boundary="periodic", storage="f32", tau=0.7) as s:
+        s.set_steps_per_launch(2)                      # 67 >= 64 + 2
+        with pytest.raises(smrt.SmrtError):
+            s.set_steps_per_launch(3)                  # periodic, nx < 64 + 4
+        with pytest.raises(smrt.SmrtError):
+            s.set_steps_per_launch(3, tile_rows=4)     # tile not offered
+        with pytest.raises(smrt.SmrtError):
+            s.set_steps_per_launch(4)
+
+
 def test_two_step_kernel_against_oracle(smrt):
     n, u, steps = 96, 0.1, 600
     with smrt.Solver(n, n, scheme="smrt", boundary="cavity", storage="f32", re=300.0, u_lid=u) as s:
