@@ -499,8 +499,8 @@ def main():
     s = STORAGE_BYTES[args.storage]
     # The dominant kernel reads d(t) and writes d(t + spl) once per node per
     # launch: 9 loads + 9 stores per node whether it advances one time step
-    # (stream_collide) or two or three through LDS (stream_collide_x2 / _x3).
-    kernel_name = {1: "stream_collide", 2: "stream_collide_x2", 3: "stream_collide_x3"}[spl]
+    # (stream_collide) or several through LDS (stream_collide_x2 .. _x4).
+    kernel_name = "stream_collide" if spl == 1 else "stream_collide_x%d" % spl
     launch_ms = (window_ms - rem_ms) / q
     alg_bytes = 18 * s * cells
     achieved = alg_bytes / (launch_ms / 1e3) / 1e9

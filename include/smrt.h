@@ -157,25 +157,25 @@ double smrt_tau(const smrt_ctx* c);
  * SMRT_EINVAL otherwise. */
 int smrt_set_launch(smrt_ctx* c, int32_t bx, int32_t by, int32_t rows);
 
-/* Time steps per kernel launch: 1, 2 or 3.  The multi-step kernels (FP32
- * and 16-bit storage only) keep the intermediate steps on chip: two steps
- * hold step t+1 of the tile plus a one-node ring in LDS; three steps hold
- * step t+1 on the tile plus a two-node ring, then step t+2 on the tile plus a
- * one-node ring.  HBM traffic per node-update falls to 1/2 or 1/3.  Tiles
- * (tile_cols x tile_rows): two steps {64 x 4, 64 x 8, 64 x 16, 64 x 32,
- * 128 x 4, 128 x 8} (0 = 64 x 8); three steps {64 x 8, 64 x 16} (0 = 64 x
- * 16); tiles of 1024 nodes or more run 512 threads per workgroup, smaller ones
- * 256.  A periodic lattice needs nx >= tile_cols + 2r and ny >= tile_rows + 2r
- * with r = steps - 1.  Per node the arithmetic is unchanged: results are
- * bitwise those of single-step launches.  Default at creation (FP32 and
- * 16-bit storage): 3 steps with a 64 x 16 tile while that gives >= 1024
- * tiles; else 2 steps with a 64 x 32 tile while that gives >= 512 tiles,
- * else with 64 x 4; FP64 and lattices too small for the rings: 1.  A step
- * count that is not a multiple ends with a two- or one-step launch.
- * SMRT_EINVAL if not applicable. */
+/* Time steps per kernel launch: 1 .. 4.  The multi-step kernels (FP32 and
+ * 16-bit storage only) keep the intermediate steps on chip: with S steps,
+ * step t+1 is held in LDS on the tile plus a ring of S - 1 nodes, each later
+ * step on a ring one node narrower, written over the same LDS.  HBM traffic
+ * per node-update falls to 1/S.  Tiles (tile_cols x tile_rows): two steps
+ * {64 x 4, 64 x 8, 64 x 16, 64 x 32, 128 x 4, 128 x 8} (0 = 64 x 8); three
+ * and four steps {64 x 8, 64 x 16} (0 = 64 x 16); tiles of 1024 nodes or more
+ * run 512 threads per workgroup, smaller ones 256.  A periodic lattice needs
+ * nx >= tile_cols + 2r and ny >= tile_rows + 2r with r = steps - 1.  Per node
+ * the arithmetic is unchanged: results are bitwise those of single-step
+ * launches.  Default at creation, with a 64 x 16 tile: FP32 storage 4 steps
+ * while that gives >= 256 tiles, 16-bit storage 3 steps while that gives >=
+ * 1024; smaller lattices 2 steps with a 64 x 32 tile while that gives >= 512
+ * tiles, else with 64 x 4; FP64 and lattices too small for the rings: 1.
+ * A step count that is not a multiple ends with one shorter launch with the
+ * same tile.  SMRT_EINVAL if not applicable. */
 int smrt_set_steps_per_launch(smrt_ctx* c, int32_t steps, int32_t tile_cols, int32_t tile_rows);
 
-/* Time steps per launch in use (1, 2 or 3); -1 for c == NULL. */
+/* Time steps per launch in use (1 .. 4); -1 for c == NULL. */
 int32_t smrt_get_steps_per_launch(const smrt_ctx* c);
 
 /* Order in which the two-step kernel's workgroups take their tiles (a
@@ -241,9 +241,10 @@ size_t smrt_batch_workspace_bytes(const smrt_batch_params* p);
 /* Creates a batch, every cavity at the cold start (rho = 1, u = 0), all
  * running.  dev_ws as for smrt_create (caller-owned or NULL).  The library
  * also allocates small device tables, a pinned host buffer and one private
- * capture stream (default priority).  Default launch: three time steps per
- * launch with 64 x 16 tiles (FP64 storage: one step, 64 x 4 blocks), one
- * workgroup per tile.  Errors as for smrt_create. */
+ * capture stream (default priority).  Default launch: 64 x 16 tiles with
+ * four time steps per launch (FP32 storage) or three (16-bit storage); FP64
+ * storage one step with 64 x 4 blocks; one workgroup per tile.  Errors as for
+ * smrt_create. */
 int smrt_batch_create(const smrt_batch_params* p, void* dev_ws, size_t ws_bytes, smrt_batch** out);
 
 /* Enqueues n time steps of every running cavity (asynchronous). */
@@ -263,7 +264,8 @@ int smrt_batch_run(smrt_batch* b, double tol, int64_t window, int64_t max_steps,
  * of resident workgroups of the batch kernel by timing `steps` real steps (an
  * even number >= 2) of each candidate (the one-step shapes, and except for
  * FP64 storage the two-step kernel with 64 x 4, 64 x 8 and 64 x 16 tiles and
- * the three-step kernel with 64 x 8 and 64 x 16 tiles); keeps the fastest.
+ * the three- and four-step kernels with 64 x 8 and 64 x 16 tiles); keeps the
+ * fastest.
  * chosen (host [3], may be NULL) receives bx, by and the grid size;
  * smrt_batch_steps_per_launch reports the steps per launch.  The trial steps
  * advance every running cavity. */
@@ -285,7 +287,7 @@ int64_t smrt_batch_steps_done(const smrt_batch* b);
 /* Number of cavities still running. */
 int32_t smrt_batch_running(const smrt_batch* b);
 
-/* Time steps per launch in use (1, 2 or 3); -1 for b == NULL. */
+/* Time steps per launch in use (1 .. 4); -1 for b == NULL. */
 int32_t smrt_batch_steps_per_launch(const smrt_batch* b);
 
 /* Frees what the library allocated (not the caller's workspace). NULL: no-op. */

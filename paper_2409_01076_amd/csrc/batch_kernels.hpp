@@ -101,75 +101,68 @@ __global__ void __launch_bounds__(1024) batch_stream_collide(const CavityDesc* _
     }
 }
 
-// Two time steps of every listed tile per launch: the batch form of
-// stream_collide_x2 (same two phases through LDS), for tiles of TX x TY
-// nodes and NT threads.  Cavity walls need no wrap, so any size works.
+// S time steps of every listed tile per launch: the batch form of the
+// multi-step kernels (stream_collide_x2 / _x3 / _x4, same phases through LDS), for
+// tiles of TX x TY nodes and NT threads.  Cavity walls need no wrap, so any
+// size works.
+template <typename T, int SCHEME, int TX, int TY, int NT, int S>
+__device__ __forceinline__ void batch_multi(const CavityDesc* __restrict__ cav, const int2* __restrict__ tiles,
+                                            const int* __restrict__ ntiles_p, T* __restrict__ base, int parity,
+                                            MultiTile<T, TX, TY, S>& sh)
+{
+    using C = typename Storage<T>::C;
+    const int ntiles = *ntiles_p;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int2 tt = tiles[t];
+        const CavityDesc c = load_desc(cav, __builtin_amdgcn_readfirstlane(tt.x));
+        const int ti = __builtin_amdgcn_readfirstlane(tt.y);
+        Geom g;
+        g.nx = c.nx;
+        g.ny = c.ny;
+        g.pitch = c.pitch;
+        g.plane = c.plane;
+        g.bx = TX;
+        g.by = TY;
+        g.rows = 1;
+        g.tiles_x = c.tiles_x;
+        g.panel = 0;
+        const T* src = base + (parity ? c.off[1] : c.off[0]);
+        T* dst = base + (parity ? c.off[0] : c.off[1]);
+        const Coef<C> k = coef_of<C>(c);
+        const int X0 = (ti % c.tiles_x) * TX, Y0 = (ti / c.tiles_x) * TY;
+        multi_tile<T, SCHEME, CAVITY, TX, TY, NT, S>(src, dst, g, k, X0, Y0, sh);
+        __syncthreads(); // the next tile reuses the LDS
+    }
+}
+
 template <typename T, int SCHEME, int TX, int TY, int NT>
 __global__ void __launch_bounds__(NT) batch_stream_collide_x2(const CavityDesc* __restrict__ cav,
                                                               const int2* __restrict__ tiles,
                                                               const int* __restrict__ ntiles_p,
                                                               T* __restrict__ base, int parity)
 {
-    using C = typename Storage<T>::C;
-    __shared__ X2Tile<T, TX, TY, NT> sh;
-    const int ntiles = *ntiles_p;
-    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const int2 tt = tiles[t];
-        const CavityDesc c = load_desc(cav, __builtin_amdgcn_readfirstlane(tt.x));
-        const int ti = __builtin_amdgcn_readfirstlane(tt.y);
-        Geom g;
-        g.nx = c.nx;
-        g.ny = c.ny;
-        g.pitch = c.pitch;
-        g.plane = c.plane;
-        g.bx = TX;
-        g.by = TY;
-        g.rows = 1;
-        g.tiles_x = c.tiles_x;
-        g.panel = 0;
-        const T* src = base + (parity ? c.off[1] : c.off[0]);
-        T* dst = base + (parity ? c.off[0] : c.off[1]);
-        const Coef<C> k = coef_of<C>(c);
-        const int X0 = (ti % c.tiles_x) * TX, Y0 = (ti / c.tiles_x) * TY;
-        x2_phase1<T, SCHEME, CAVITY, TX, TY, NT>(src, g, k, X0, Y0, sh);
-        __syncthreads();
-        x2_phase2<T, SCHEME, CAVITY, TX, TY, NT>(dst, g, k, X0, Y0, sh);
-        __syncthreads(); // the next tile reuses the LDS
-    }
+    __shared__ MultiTile<T, TX, TY, 2> sh;
+    batch_multi<T, SCHEME, TX, TY, NT, 2>(cav, tiles, ntiles_p, base, parity, sh);
 }
 
-// Three time steps of every listed tile per launch: the batch form of
-// stream_collide_x3, for tiles of TX x TY nodes and NT threads.
 template <typename T, int SCHEME, int TX, int TY, int NT>
 __global__ void __launch_bounds__(NT) batch_stream_collide_x3(const CavityDesc* __restrict__ cav,
                                                               const int2* __restrict__ tiles,
                                                               const int* __restrict__ ntiles_p,
                                                               T* __restrict__ base, int parity)
 {
-    using C = typename Storage<T>::C;
-    __shared__ X3Tile<T, TX, TY> sh;
-    const int ntiles = *ntiles_p;
-    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const int2 tt = tiles[t];
-        const CavityDesc c = load_desc(cav, __builtin_amdgcn_readfirstlane(tt.x));
-        const int ti = __builtin_amdgcn_readfirstlane(tt.y);
-        Geom g;
-        g.nx = c.nx;
-        g.ny = c.ny;
-        g.pitch = c.pitch;
-        g.plane = c.plane;
-        g.bx = TX;
-        g.by = TY;
-        g.rows = 1;
-        g.tiles_x = c.tiles_x;
-        g.panel = 0;
-        const T* src = base + (parity ? c.off[1] : c.off[0]);
-        T* dst = base + (parity ? c.off[0] : c.off[1]);
-        const Coef<C> k = coef_of<C>(c);
-        const int X0 = (ti % c.tiles_x) * TX, Y0 = (ti / c.tiles_x) * TY;
-        x3_tile<T, SCHEME, CAVITY, TX, TY, NT>(src, dst, g, k, X0, Y0, sh);
-        __syncthreads(); // the next tile reuses the LDS
-    }
+    __shared__ MultiTile<T, TX, TY, 3> sh;
+    batch_multi<T, SCHEME, TX, TY, NT, 3>(cav, tiles, ntiles_p, base, parity, sh);
+}
+
+template <typename T, int SCHEME, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT) batch_stream_collide_x4(const CavityDesc* __restrict__ cav,
+                                                              const int2* __restrict__ tiles,
+                                                              const int* __restrict__ ntiles_p,
+                                                              T* __restrict__ base, int parity)
+{
+    __shared__ MultiTile<T, TX, TY, 4> sh;
+    batch_multi<T, SCHEME, TX, TY, NT, 4>(cav, tiles, ntiles_p, base, parity, sh);
 }
 
 // Per-tile FP64 partial sums (|u - u_snap|^2, |u|^2, rho - 1, non-finite

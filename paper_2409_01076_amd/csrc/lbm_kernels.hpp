@@ -204,60 +204,69 @@ __device__ __forceinline__ double reciprocal(double x) { return 1.0 / x; }
 template <int SCHEME, typename T, typename C = typename Storage<T>::C>
 __device__ __forceinline__ void collide(C d[9], const Coef<C>& k)
 {
-    const C drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
-    const C jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
-    const C jy = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
+    // Sums and differences of the opposite pairs (1,3), (2,4), (5,7), (6,8)
+    // give the moments and, below, the group sums with few operations.
+    const C p13 = d[1] + d[3], p24 = d[2] + d[4], p57 = d[5] + d[7], p68 = d[6] + d[8];
+    const C m13 = d[1] - d[3], m24 = d[2] - d[4], m57 = d[5] - d[7], m68 = d[6] - d[8];
+    const C drho = d[0] + ((p13 + p24) + (p57 + p68));
+    const C jx = m13 + (m57 - m68); // e_x = +1 for 1, 5, 8 and -1 for 3, 6, 7
+    const C jy = m24 + (m57 + m68); // e_y = +1 for 2, 5, 6 and -1 for 4, 7, 8
     const C inv = reciprocal(C(1) + drho);
     const C ux = jx * inv, uy = jy * inv;
-    const C base = drho - C(1.5) * (jx * ux + jy * uy);
+    const C jxux = jx * ux, jyuy = jy * uy;
+    const C base = drho - C(1.5) * (jxux + jyuy);
 
     const C e5j = jx + jy, e5u = ux + uy; // e_5 = (1, 1) = -e_7
     const C e6j = jy - jx, e6u = uy - ux; // e_6 = (-1, 1) = -e_8
-    const C sx = W<C>::axis * (base + C(4.5) * jx * ux);
-    const C sy = W<C>::axis * (base + C(4.5) * jy * uy);
-    const C s5 = W<C>::diag * (base + C(4.5) * e5j * e5u);
-    const C s6 = W<C>::diag * (base + C(4.5) * e6j * e6u);
+    // s = w (base + 9/2 (e.j)(e.u)), with w base formed once per class
+    const C abase = W<C>::axis * base, dbase = W<C>::diag * base;
+    const C sx = abase + (C(4.5) * W<C>::axis) * jxux;
+    const C sy = abase + (C(4.5) * W<C>::axis) * jyuy;
+    const C s5 = dbase + (C(4.5) * W<C>::diag) * (e5j * e5u);
+    const C s6 = dbase + (C(4.5) * W<C>::diag) * (e6j * e6u);
     const C t5 = C(1.0 / 12.0) * e5j; // 3 w_diag (e_5 . j)
     const C t6 = C(1.0 / 12.0) * e6j;
     const C tx = C(0.5) * jx - (t5 - t6);
     const C ty = C(0.5) * jy - (t5 + t6);
 
-    C q[9];
-    q[0] = drho - C(2) * ((sx + sy) + (s5 + s6));
-    q[1] = sx + tx;
-    q[3] = sx - tx;
-    q[2] = sy + ty;
-    q[4] = sy - ty;
-    q[5] = s5 + t5;
-    q[7] = s5 - t5;
-    q[6] = s6 + t6;
-    q[8] = s6 - t6;
-
-    if constexpr (SCHEME == SRT) {
-        // Eq. (lb.srt): f* = f - (f - f^eq)/tau
-#pragma unroll
-        for (int a = 0; a < 9; ++a) d[a] = d[a] + k.omega * (q[a] - d[a]);
-    } else {
+    if constexpr (SCHEME == SMRT) {
         // Group sums of Eq. (sigma1-2-0): C_1 over the axis links, C_2 over the
-        // diagonal links, each sum_k (-1)^k (f_k - f^eq_k) / 4.  The odd parts
-        // cancel in the equilibrium's share (q_2 + q_4 - q_1 - q_3 = 2 (s_y - s_x),
-        // q_6 + q_8 - q_5 - q_7 = 2 (s_6 - s_5)).
-        const C c1 = C(0.25) * ((d[2] + d[4]) - (d[1] + d[3])) - C(0.5) * (sy - sx);
-        const C c2 = C(0.25) * ((d[6] + d[8]) - (d[5] + d[7])) - C(0.5) * (s6 - s5);
-        if constexpr (SCHEME == SMRT) {
-            // Eq. (SmrtLBM-1): f*_a = f^eq_a + (-1)^a (1 - 1/tau) C_g(a)
-            const C g1 = k.a * c1, g2 = k.a * c2;
-            d[0] = q[0];
-            d[1] = q[1] - g1;
-            d[2] = q[2] + g1;
-            d[3] = q[3] - g1;
-            d[4] = q[4] + g1;
-            d[5] = q[5] - g2;
-            d[6] = q[6] + g2;
-            d[7] = q[7] - g2;
-            d[8] = q[8] + g2;
+        // diagonal links, each sum_k (-1)^k (f_k - f^eq_k) / 4; the odd parts
+        // cancel in the equilibrium's share (q_2 + q_4 - q_1 - q_3 = 2 (s_y -
+        // s_x), q_6 + q_8 - q_5 - q_7 = 2 (s_6 - s_5)).
+        const C c1 = C(0.25) * (p24 - p13) - C(0.5) * (sy - sx);
+        const C c2 = C(0.25) * (p68 - p57) - C(0.5) * (s6 - s5);
+        // Eq. (SmrtLBM-1): f*_a = f^eq_a + (-1)^a (1 - 1/tau) C_g(a); both
+        // members of an opposite pair get the same correction.
+        const C g1 = k.a * c1, g2 = k.a * c2;
+        const C ax = sx - g1, ay = sy + g1, a5 = s5 - g2, a6 = s6 + g2;
+        d[1] = ax + tx;
+        d[3] = ax - tx;
+        d[2] = ay + ty;
+        d[4] = ay - ty;
+        d[5] = a5 + t5;
+        d[7] = a5 - t5;
+        d[6] = a6 + t6;
+        d[8] = a6 - t6;
+    } else {
+        C q[9];
+        q[0] = drho - C(2) * ((sx + sy) + (s5 + s6));
+        q[1] = sx + tx;
+        q[3] = sx - tx;
+        q[2] = sy + ty;
+        q[4] = sy - ty;
+        q[5] = s5 + t5;
+        q[7] = s5 - t5;
+        q[6] = s6 + t6;
+        q[8] = s6 - t6;
+        if constexpr (SCHEME == SRT) {
+            // Eq. (lb.srt): f* = f - (f - f^eq)/tau
+#pragma unroll
+            for (int a = 0; a < 9; ++a) d[a] = d[a] + k.omega * (q[a] - d[a]);
         } else {
             // Eq. (SmrtLBM-lb.1.5): f*_a = f_a - (f_a - f^eq_a)/tau_s + (-1)^a (1/tau_s - 1/tau) C_g(a)
+            const C c1 = C(0.25) * (p24 - p13) - C(0.5) * (sy - sx);
+            const C c2 = C(0.25) * (p68 - p57) - C(0.5) * (s6 - s5);
             const C g1 = k.b * c1, g2 = k.b * c2;
 #pragma unroll
             for (int a = 0; a < 9; ++a) d[a] = d[a] + k.omega_s * (q[a] - d[a]);
@@ -438,13 +447,6 @@ __global__ void __launch_bounds__(1024) stream_collide(const T* __restrict__ src
 // arithmetic is that of stream_collide (same gather, collide and, for 16-bit
 // storage, the same rounding to the storage grid between the steps), so the
 // results are bitwise those of two one-step launches.
-constexpr int X2_THREADS = 256;
-
-template <typename T, int TX, int TY, int NT = X2_THREADS> struct X2Tile {
-    using C = typename Storage<T>::C;
-    static constexpr int RX = TX + 2, RY = TY + 2;
-    C mid[9][RY][RX]; // step t+1 on the tile plus a one-node ring (LDS)
-};
 
 // The first step of a multi-step launch, in two halves over a region of
 // RX x RY nodes: the tile (X0, Y0, TX x TY) plus a ring of RING nodes.
@@ -552,26 +554,6 @@ __device__ __forceinline__ void lds_to_hbm(T* __restrict__ dst, const Geom& g, c
     }
 }
 
-// Phase 1 of the two-step launch: step t+1 on the tile plus a one-node ring,
-// into LDS.  A periodic lattice needs nx >= TX + 2 and ny >= TY + 2.
-template <typename T, int SCHEME, int BC, int TX, int TY, int NT = X2_THREADS>
-__device__ __forceinline__ void x2_phase1(const T* __restrict__ src, const Geom& g,
-                                          const Coef<typename Storage<T>::C>& k, int X0, int Y0,
-                                          X2Tile<T, TX, TY, NT>& sh)
-{
-    RingRegs<T, TX + 2, TY + 2, NT> r;
-    ring_load<T, BC, TX + 2, TY + 2, NT, 1>(src, g, k.lid, X0, Y0, r);
-    ring_collide<T, SCHEME, TX + 2, TY + 2, NT>(k, r, sh.mid);
-}
-
-// Phase 2 of the two-step launch: pull step t+1 from LDS, collide, store t+2.
-template <typename T, int SCHEME, int BC, int TX, int TY, int NT = X2_THREADS>
-__device__ __forceinline__ void x2_phase2(T* __restrict__ dst, const Geom& g, const Coef<typename Storage<T>::C>& k,
-                                          int X0, int Y0, const X2Tile<T, TX, TY, NT>& sh)
-{
-    lds_to_hbm<T, SCHEME, BC, TX, TY, NT>(dst, g, k, X0, Y0, sh.mid);
-}
-
 // Tile of this workgroup (row-major or XCD panel order).
 __device__ __forceinline__ void workgroup_tile(const Geom& g, int TX, int TY, int& X0, int& Y0)
 {
@@ -583,85 +565,110 @@ __device__ __forceinline__ void workgroup_tile(const Geom& g, int TX, int TY, in
     Y0 = ty * TY;
 }
 
-template <typename T, int SCHEME, int BC, int TX, int TY, int NT>
-__global__ void __launch_bounds__(NT) stream_collide_x2(const T* __restrict__ src, T* __restrict__ dst, Geom g,
-                                                        Coef<typename Storage<T>::C> k)
-{
-    __shared__ X2Tile<T, TX, TY, NT> sh;
-    int X0, Y0;
-    workgroup_tile(g, TX, TY, X0, Y0);
-    x2_phase1<T, SCHEME, BC, TX, TY, NT>(src, g, k, X0, Y0, sh);
-    __syncthreads();
-    x2_phase2<T, SCHEME, BC, TX, TY, NT>(dst, g, k, X0, Y0, sh);
-}
-
-// Three time steps per launch.  Step t+1 on the tile plus a two-node ring
-// goes to LDS (a); step t+2 on the tile plus a one-node ring is pulled from
-// it, collided into registers and, after a barrier, written over the same
-// LDS (b); step t+3 is pulled from b and stored.  HBM traffic per
-// node-update falls to a third of a one-step launch; the rings add
-// ((TX+4)(TY+4) + (TX+2)(TY+2)) / (TX TY) - 2 redundant collisions.  Same
-// per-node arithmetic, so the results are bitwise those of three one-step
-// launches.  A periodic lattice needs nx >= TX + 4 and ny >= TY + 4.
-template <typename T, int TX, int TY> struct X3Tile {
+// S time steps per launch (S = 2, 3, 4) on a TX x TY tile.  Step t+1 is
+// computed on the tile plus a ring of S - 1 nodes (pulled from HBM) into LDS;
+// each further step t+s (s < S) is pulled from LDS on the tile plus a ring of
+// S - s nodes, collided into registers and, after a barrier, written over the
+// same LDS; step t+S is pulled from LDS for the tile only and stored.  HBM
+// traffic per node-update falls to 1/S of a one-step launch; the rings add
+// sum_r (TX + 2r)(TY + 2r) / (TX TY) - (S - 1) redundant collisions.  Same
+// per-node arithmetic, so the results are bitwise those of S one-step
+// launches.  A periodic lattice needs nx >= TX + 2(S - 1), ny >= TY + 2(S - 1).
+template <typename T, int TX, int TY, int S> struct MultiTile {
     using C = typename Storage<T>::C;
-    union {
-        C a[9][TY + 4][TX + 4]; // step t+1
-        C b[9][TY + 2][TX + 2]; // step t+2, written over a
-    };
+    static constexpr int R = S - 1;
+    C buf[9 * (TX + 2 * R) * (TY + 2 * R)];
+    // the LDS viewed as the step held on the tile plus a ring of r nodes
+    template <int r> __device__ C (&ring())[9][TY + 2 * r][TX + 2 * r]
+    {
+        return *reinterpret_cast<C(*)[9][TY + 2 * r][TX + 2 * r]>(buf);
+    }
 };
 
-template <typename T, int SCHEME, int BC, int TX, int TY, int NT>
-__device__ __forceinline__ void x3_tile(const T* __restrict__ src, T* __restrict__ dst, const Geom& g,
-                                        const Coef<typename Storage<T>::C>& k, int X0, int Y0, X3Tile<T, TX, TY>& sh)
+// A middle step: pull from the ring-(r+1) step in LDS, collide on the tile
+// plus a ring of r nodes, then (after every pull is done) write over the LDS.
+template <typename T, int SCHEME, int BC, int TX, int TY, int NT, int S, int r>
+__device__ __forceinline__ void middle_step(const Geom& g, const Coef<typename Storage<T>::C>& k, int X0, int Y0,
+                                            MultiTile<T, TX, TY, S>& sh)
 {
     using C = typename Storage<T>::C;
-    constexpr int AX = TX + 4, AY = TY + 4, BX = TX + 2, BY = TY + 2;
-    constexpr int P2 = (BX * BY + NT - 1) / NT;
-    {
-        RingRegs<T, AX, AY, NT> r;
-        ring_load<T, BC, AX, AY, NT, 2>(src, g, k.lid, X0, Y0, r);
-        ring_collide<T, SCHEME, AX, AY, NT>(k, r, sh.a);
-    }
-    __syncthreads();
-    C d[P2][9];
-    bool live[P2];
+    constexpr int BX = TX + 2 * r, BY = TY + 2 * r, AX = BX + 2, AY = BY + 2;
+    constexpr int P = (BX * BY + NT - 1) / NT;
+    C d[P][9];
+    bool live[P];
 #pragma unroll
-    for (int j = 0; j < P2; ++j) {
+    for (int j = 0; j < P; ++j) {
         const int i = threadIdx.x + j * NT;
         const int lx = i % BX, ly = i / BX;
-        const int x = X0 - 1 + lx, y = Y0 - 1 + ly; // unwrapped
+        const int x = X0 - r + lx, y = Y0 - r + ly; // unwrapped
         if constexpr (BC == PERIODIC)
-            live[j] = i < BX * BY && x <= g.nx && y <= g.ny;
+            live[j] = i < BX * BY && x <= g.nx + r - 1 && y <= g.ny + r - 1;
         else
             live[j] = i < BX * BY && (unsigned)x < (unsigned)g.nx && (unsigned)y < (unsigned)g.ny;
         if (live[j]) {
-            pull_lds<T, BC, AX, AY>(sh.a, g, k.lid, lx + 1, ly + 1, x, y, d[j]);
+            pull_lds<T, BC, AX, AY>(sh.template ring<r + 1>(), g, k.lid, lx + 1, ly + 1, x, y, d[j]);
             collide<SCHEME, T>(d[j], k);
             if constexpr (Storage<T>::kRounds) d[j][0] = Storage<T>::stored_value(d[j][0], 0);
         }
     }
-    __syncthreads(); // every pull from a is done before b overwrites it
+    __syncthreads(); // every pull from the wider ring is done before it is overwritten
+    auto& m = sh.template ring<r>();
 #pragma unroll
-    for (int j = 0; j < P2; ++j) {
+    for (int j = 0; j < P; ++j) {
         if (!live[j]) continue;
         const int i = threadIdx.x + j * NT;
         const int lx = i % BX, ly = i / BX;
 #pragma unroll
-        for (int a = 0; a < 9; ++a) sh.b[a][ly][lx] = d[j][a];
+        for (int a = 0; a < 9; ++a) m[a][ly][lx] = d[j][a];
     }
     __syncthreads();
-    lds_to_hbm<T, SCHEME, BC, TX, TY, NT>(dst, g, k, X0, Y0, sh.b);
+}
+
+template <typename T, int SCHEME, int BC, int TX, int TY, int NT, int S>
+__device__ __forceinline__ void multi_tile(const T* __restrict__ src, T* __restrict__ dst, const Geom& g,
+                                           const Coef<typename Storage<T>::C>& k, int X0, int Y0,
+                                           MultiTile<T, TX, TY, S>& sh)
+{
+    constexpr int R = S - 1;
+    {
+        RingRegs<T, TX + 2 * R, TY + 2 * R, NT> r;
+        ring_load<T, BC, TX + 2 * R, TY + 2 * R, NT, R>(src, g, k.lid, X0, Y0, r);
+        ring_collide<T, SCHEME, TX + 2 * R, TY + 2 * R, NT>(k, r, sh.template ring<R>());
+    }
+    __syncthreads();
+    if constexpr (R >= 3) middle_step<T, SCHEME, BC, TX, TY, NT, S, 2>(g, k, X0, Y0, sh);
+    if constexpr (R >= 2) middle_step<T, SCHEME, BC, TX, TY, NT, S, 1>(g, k, X0, Y0, sh);
+    lds_to_hbm<T, SCHEME, BC, TX, TY, NT>(dst, g, k, X0, Y0, sh.template ring<1>());
+}
+
+template <typename T, int SCHEME, int BC, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT) stream_collide_x2(const T* __restrict__ src, T* __restrict__ dst, Geom g,
+                                                        Coef<typename Storage<T>::C> k)
+{
+    __shared__ MultiTile<T, TX, TY, 2> sh;
+    int X0, Y0;
+    workgroup_tile(g, TX, TY, X0, Y0);
+    multi_tile<T, SCHEME, BC, TX, TY, NT, 2>(src, dst, g, k, X0, Y0, sh);
 }
 
 template <typename T, int SCHEME, int BC, int TX, int TY, int NT>
 __global__ void __launch_bounds__(NT) stream_collide_x3(const T* __restrict__ src, T* __restrict__ dst, Geom g,
                                                         Coef<typename Storage<T>::C> k)
 {
-    __shared__ X3Tile<T, TX, TY> sh;
+    __shared__ MultiTile<T, TX, TY, 3> sh;
     int X0, Y0;
     workgroup_tile(g, TX, TY, X0, Y0);
-    x3_tile<T, SCHEME, BC, TX, TY, NT>(src, dst, g, k, X0, Y0, sh);
+    multi_tile<T, SCHEME, BC, TX, TY, NT, 3>(src, dst, g, k, X0, Y0, sh);
+}
+
+template <typename T, int SCHEME, int BC, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT) stream_collide_x4(const T* __restrict__ src, T* __restrict__ dst, Geom g,
+                                                        Coef<typename Storage<T>::C> k)
+{
+    __shared__ MultiTile<T, TX, TY, 4> sh;
+    int X0, Y0;
+    workgroup_tile(g, TX, TY, X0, Y0);
+    multi_tile<T, SCHEME, BC, TX, TY, NT, 4>(src, dst, g, k, X0, Y0, sh);
 }
 
 // ---------------------------------------------------------------------------

@@ -198,7 +198,7 @@ struct smrt_ctx {
     int cur = 0;                   // 0: state in buffer A, 1: in buffer B
     int64_t steps = 0, snap_step = 0;
     int bx = 256, by = 1, rows = 1;
-    int fused = 1;                 // time steps per launch (1, or 2 / 3 with the LDS-blocked kernels)
+    int fused = 1;                 // time steps per launch (1, or 2 .. 4 with the LDS-blocked kernels)
     int fused_cols = 64, fused_rows = 8; // tile of the two-step kernel
     int panel = 0;                 // two-step kernel: tile order (0 = row-major)
 
@@ -268,25 +268,21 @@ template <typename T> int launch_step(smrt_ctx* c, const void* src, void* dst)
 // Threads per two-step workgroup: 512 for tiles of 1024 nodes or more.
 constexpr int x2_threads(int tx, int ty) { return tx * ty >= 1024 ? 512 : 256; }
 
-template <typename T, int SCHEME, int BC, int TX, int TY>
-int launch_x2(smrt_ctx* c, const T* s, T* d, const smrt::Geom& g, const smrt::Coef<typename smrt::Storage<T>::C>& k,
-              int ntiles)
+template <typename T, int SCHEME, int BC, int TX, int TY, int STEPS>
+int launch_multi(smrt_ctx* c, const T* s, T* d, const smrt::Geom& g,
+                 const smrt::Coef<typename smrt::Storage<T>::C>& k, int ntiles)
 {
     constexpr int NT = x2_threads(TX, TY);
-    smrt::stream_collide_x2<T, SCHEME, BC, TX, TY, NT><<<ntiles, NT, 0, c->stream>>>(s, d, g, k);
+    if constexpr (STEPS == 4)
+        smrt::stream_collide_x4<T, SCHEME, BC, TX, TY, NT><<<ntiles, NT, 0, c->stream>>>(s, d, g, k);
+    else if constexpr (STEPS == 3)
+        smrt::stream_collide_x3<T, SCHEME, BC, TX, TY, NT><<<ntiles, NT, 0, c->stream>>>(s, d, g, k);
+    else
+        smrt::stream_collide_x2<T, SCHEME, BC, TX, TY, NT><<<ntiles, NT, 0, c->stream>>>(s, d, g, k);
     return SMRT_OK;
 }
 
-template <typename T, int SCHEME, int BC, int TX, int TY>
-int launch_x3(smrt_ctx* c, const T* s, T* d, const smrt::Geom& g, const smrt::Coef<typename smrt::Storage<T>::C>& k,
-              int ntiles)
-{
-    constexpr int NT = x2_threads(TX, TY);
-    smrt::stream_collide_x3<T, SCHEME, BC, TX, TY, NT><<<ntiles, NT, 0, c->stream>>>(s, d, g, k);
-    return SMRT_OK;
-}
-
-// One launch of the two-step (STEPS = 2) or three-step (STEPS = 3) kernel.
+// One launch of the STEPS-step kernel (STEPS = 2, 3, 4).
 template <typename T, int STEPS, int TX, int TY> int launch_multi_tile(smrt_ctx* c, const void* src, void* dst)
 {
     using C = typename smrt::Storage<T>::C;
@@ -310,8 +306,7 @@ template <typename T, int STEPS, int TX, int TY> int launch_multi_tile(smrt_ctx*
     const bool per = c->p.boundary == SMRT_PERIODIC;
     auto go = [&](auto scheme_tag, auto bc_tag) {
         constexpr int SCHEME = decltype(scheme_tag)::value, BC = decltype(bc_tag)::value;
-        if constexpr (STEPS == 3) return launch_x3<T, SCHEME, BC, TX, TY>(c, s, d, g, k, n);
-        else return launch_x2<T, SCHEME, BC, TX, TY>(c, s, d, g, k, n);
+        return launch_multi<T, SCHEME, BC, TX, TY, STEPS>(c, s, d, g, k, n);
     };
     using PER = std::integral_constant<int, smrt::PERIODIC>;
     using CAV = std::integral_constant<int, smrt::CAVITY>;
@@ -345,14 +340,21 @@ template <typename T> int launch_step3(smrt_ctx* c, const void* src, void* dst)
     return launch_multi_tile<T, 3, 64, 8>(c, src, dst);
 }
 
-// Three time steps in one launch (FP32 and 16-bit storage only).
-int dispatch_step3(smrt_ctx* c, const void* src, void* dst)
+// Four-step tiles offered: 64 x {8, 16}.
+template <typename T> int launch_step4(smrt_ctx* c, const void* src, void* dst)
+{
+    if (c->fused_rows == 16) return launch_multi_tile<T, 4, 64, 16>(c, src, dst);
+    return launch_multi_tile<T, 4, 64, 8>(c, src, dst);
+}
+
+// Three or four time steps in one launch (FP32 and 16-bit storage only).
+int dispatch_step34(smrt_ctx* c, int k, const void* src, void* dst)
 {
     switch (c->p.storage) {
-    case SMRT_F32: return launch_step3<float>(c, src, dst);
-    case SMRT_F16: return launch_step3<_Float16>(c, src, dst);
-    case SMRT_BF16: return launch_step3<smrt::bf16>(c, src, dst);
-    default: return fail(SMRT_EINVAL, "three-step launches need FP32 or 16-bit storage");
+    case SMRT_F32: return k == 4 ? launch_step4<float>(c, src, dst) : launch_step3<float>(c, src, dst);
+    case SMRT_F16: return k == 4 ? launch_step4<_Float16>(c, src, dst) : launch_step3<_Float16>(c, src, dst);
+    case SMRT_BF16: return k == 4 ? launch_step4<smrt::bf16>(c, src, dst) : launch_step3<smrt::bf16>(c, src, dst);
+    default: return fail(SMRT_EINVAL, "multi-step launches need FP32 or 16-bit storage");
     }
 }
 
@@ -471,17 +473,22 @@ int smrt_create(const smrt_params* p, void* dev_ws, size_t ws_bytes, smrt_ctx** 
         // Default block shape: one row segment per block, as wide as the
         // lattice allows (512 measured best on 4096^2, within 1-2% of 256).
         // FP32 and 16-bit storage take the LDS-blocked kernels, tiles in XCD
-        // panels of 8 tile columns.  Measured on 512^2 .. 4096^2: three steps
-        // per launch with 64 x 16 tiles (512 threads) while that gives >= 1024
-        // workgroups; else two steps with 64 x 32 tiles while that gives >=
-        // 512, else with 64 x 4.  Periodic lattices need room for the rings.
+        // panels of 8 tile columns.  Measured on 512^2 .. 4096^2 with 64 x 16
+        // tiles (512 threads): FP32 four steps per launch while that gives
+        // >= 256 workgroups, 16-bit storage three steps while it gives >=
+        // 1024; smaller lattices two steps with 64 x 32 tiles while that
+        // gives >= 512 workgroups, else with 64 x 4.  Periodic lattices need
+        // room for the rings.
         if (p->storage != SMRT_F64) {
-            const int64_t cols = (p->nx + 63) / 64;
+            const int64_t cols = (p->nx + 63) / 64, tiles16 = cols * ((p->ny + 15) / 16);
             const bool per = p->boundary == SMRT_PERIODIC;
+            const int deep = p->storage == SMRT_F32 ? 4 : 3;
+            const int64_t deep_min = p->storage == SMRT_F32 ? 256 : 1024;
+            const int ring = deep - 1;
             c->fused_cols = 64;
             c->panel = 8;
-            if (cols * ((p->ny + 15) / 16) >= 1024 && (!per || (p->nx >= 68 && p->ny >= 20))) {
-                c->fused = 3;
+            if (tiles16 >= deep_min && (!per || (p->nx >= 64 + 2 * ring && p->ny >= 16 + 2 * ring))) {
+                c->fused = deep;
                 c->fused_rows = 16;
             } else {
                 c->fused_rows = cols * ((p->ny + 31) / 32) >= 512 ? 32 : 4;
@@ -580,12 +587,13 @@ int smrt_step(smrt_ctx* c, int64_t n)
     if (n < 0) return fail(SMRT_EINVAL, "step count must be >= 0 (got %lld)", (long long)n);
     int64_t left = n;
     while (left > 0) {
-        // the largest launch that fits: fused steps, then 2 (the three-step
-        // tiles are also two-step tiles), then 1
+        // the largest launch that fits: fused steps, then fewer with the same
+        // tile (every three- and four-step tile is also a two-step tile)
         const int k = (int)std::min<int64_t>(c->fused, left);
         const void* src = c->buffer(c->cur);
         void* dst = c->buffer(c->cur ^ 1);
-        int rc = k == 3 ? dispatch_step3(c, src, dst) : k == 2 ? dispatch_step2(c, src, dst) : dispatch_step(c, src, dst);
+        int rc = k >= 3 ? dispatch_step34(c, k, src, dst)
+                        : k == 2 ? dispatch_step2(c, src, dst) : dispatch_step(c, src, dst);
         if (rc) return rc;
         c->cur ^= 1;
         c->steps += k;
@@ -668,10 +676,10 @@ int smrt_set_launch(smrt_ctx* c, int32_t bx, int32_t by, int32_t rows)
 int smrt_set_steps_per_launch(smrt_ctx* c, int32_t steps, int32_t tile_cols, int32_t tile_rows)
 {
     if (!c) return fail(SMRT_EINVAL, "context is NULL");
-    if (steps < 1 || steps > 3) return fail(SMRT_EINVAL, "steps per launch must be 1, 2 or 3 (got %d)", steps);
+    if (steps < 1 || steps > 4) return fail(SMRT_EINVAL, "steps per launch must be 1 .. 4 (got %d)", steps);
     if (tile_cols == 0) tile_cols = 64;
-    if (tile_rows == 0) tile_rows = steps == 3 ? 16 : 8;
-    const bool ok = steps == 3 ? tile_cols == 64 && (tile_rows == 8 || tile_rows == 16)
+    if (tile_rows == 0) tile_rows = steps >= 3 ? 16 : 8;
+    const bool ok = steps >= 3 ? tile_cols == 64 && (tile_rows == 8 || tile_rows == 16)
                                : (tile_cols == 64 && (tile_rows == 4 || tile_rows == 8 || tile_rows == 16 ||
                                                       tile_rows == 32)) ||
                                      (tile_cols == 128 && (tile_rows == 4 || tile_rows == 8));

@@ -237,11 +237,25 @@ void launch_three_tile(smrt_batch* b, hipStream_t s, int parity, dim3 grid)
         b->desc(), b->table(), b->ntiles_dev(), reinterpret_cast<T*>(b->state()), parity);
 }
 
-// One launch of k time steps (k = 2, 3: 64 x shape.by tiles; the tile table
-// is built for that shape, so a shorter remainder launch uses the same table).
+template <typename T, int SCHEME, int TY>
+void launch_four_tile(smrt_batch* b, hipStream_t s, int parity, dim3 grid)
+{
+    constexpr int NT = two_threads(TY);
+    smrt::batch_stream_collide_x4<T, SCHEME, 64, TY, NT><<<grid, NT, 0, s>>>(
+        b->desc(), b->table(), b->ntiles_dev(), reinterpret_cast<T*>(b->state()), parity);
+}
+
+// One launch of k time steps (k = 2, 3, 4: 64 x shape.by tiles; the tile
+// table is built for that shape, so a shorter remainder launch uses the same
+// table).
 template <typename T, int SCHEME> void launch_typed_scheme(smrt_batch* b, hipStream_t s, int parity, int k)
 {
     dim3 grid((unsigned)std::max(b->grid, 1));
+    if (k == 4) {
+        if (b->shape.by == 16) launch_four_tile<T, SCHEME, 16>(b, s, parity, grid);
+        else launch_four_tile<T, SCHEME, 8>(b, s, parity, grid);
+        return;
+    }
     if (k == 3) {
         if (b->shape.by == 16) launch_three_tile<T, SCHEME, 16>(b, s, parity, grid);
         else launch_three_tile<T, SCHEME, 8>(b, s, parity, grid);
@@ -267,8 +281,8 @@ template <typename T> void launch_step_typed(smrt_batch* b, hipStream_t s, int p
     }
 }
 
-// One launch of k = 1, 2 or 3 time steps (FP64 storage has only the
-// one-step kernel).
+// One launch of k = 1 .. 4 time steps (FP64 storage has only the one-step
+// kernel).
 void launch_step(smrt_batch* b, hipStream_t s, int parity, int k)
 {
     switch (b->p.storage) {
@@ -455,10 +469,10 @@ int smrt_batch_create(const smrt_batch_params* p, void* dev_ws, size_t ws_bytes,
             return hip_fail(e, "hipMemsetAsync");
         }
         // Default launch: one pass over the table per launch; FP64 one step
-        // per launch with 64 x 4 tiles, other storage three steps with 64 x 16
-        // tiles (the fastest on every batch of 16..256 cavities measured).
+        // per launch with 64 x 4 tiles, other storage 64 x 16 tiles with four
+        // steps per launch (FP32) or three (16-bit), as for single lattices.
         b->shape = p->storage == SMRT_F64 ? kShapes[0] : smrt::BatchLaunch{64, 16};
-        b->multi = p->storage == SMRT_F64 ? 1 : 3;
+        b->multi = p->storage == SMRT_F64 ? 1 : p->storage == SMRT_F32 ? 4 : 3;
         int total_tiles = 0;
         for (const auto& c : b->plan.desc) total_tiles += tiles_of(c.nx, c.ny, b->shape);
         b->grid = total_tiles;
@@ -559,11 +573,11 @@ int smrt_batch_autotune(smrt_batch* b, int32_t steps, int32_t* chosen)
     int best_multi = b->multi;
     int rc = SMRT_OK;
     // Candidates: every one-step shape, then (except for FP64) the two-step
-    // kernel with 64 x 4, 64 x 8 and 64 x 16 tiles and the three-step kernel
-    // with 64 x 8 and 64 x 16 tiles; times are per time step.
-    static const int kMultiSteps[] = {2, 2, 2, 3, 3};
-    static const int kMultiRows[] = {4, 8, 16, 8, 16};
-    const int n_multi = b->p.storage == SMRT_F64 ? 0 : 5;
+    // kernel with 64 x 4, 64 x 8 and 64 x 16 tiles and the three- and
+    // four-step kernels with 64 x 8 and 64 x 16 tiles; times are per time step.
+    static const int kMultiSteps[] = {2, 2, 2, 3, 3, 4, 4};
+    static const int kMultiRows[] = {4, 8, 16, 8, 16, 8, 16};
+    const int n_multi = b->p.storage == SMRT_F64 ? 0 : 7;
     for (int s = 0; s < kNumShapes + n_multi && rc == SMRT_OK; ++s) {
         const int multi = s >= kNumShapes ? kMultiSteps[s - kNumShapes] : 1;
         b->shape = multi > 1 ? smrt::BatchLaunch{64, kMultiRows[s - kNumShapes]} : kShapes[s];

@@ -407,16 +407,18 @@ def test_tile_order_does_not_change_results(smrt, boundary, tile):
 @pytest.mark.parametrize("boundary", ["periodic", "cavity"])
 @pytest.mark.parametrize("scheme", ["srt", "smrt", "trt"])
 @pytest.mark.parametrize("tile", [(64, 8), (64, 16)])
-def test_three_step_kernel_equals_single_steps(smrt, storage, boundary, scheme, tile):
-    """Three steps per launch (two LDS rings, the middle step written over
-    the first): bitwise equal to one-step launches on a ragged lattice, over
-    step counts that end with a two-step and with a one-step launch."""
+@pytest.mark.parametrize("multi", [3, 4])
+def test_multi_step_kernel_equals_single_steps(smrt, storage, boundary, scheme, tile, multi):
+    """Three or four steps per launch (nested LDS rings, each step written
+    over the previous): bitwise equal to one-step launches on a ragged
+    lattice, over step counts that end with shorter launches (41 and 43 steps:
+    remainders 2 and 1 for three steps, 1 and 3 for four)."""
     nx, ny = 203, 77
     f0 = inputs.perturbed_populations(nx, ny, eps=0.03, seed=7)
     u = 0.1 if boundary == "cavity" else 0.0
     for steps in (41, 43):
         outs = []
-        for spl in (1, 3):
+        for spl in (1, multi):
             with smrt.Solver(nx, ny, scheme=scheme, boundary=boundary, storage=storage, tau=0.56,
                              u_lid=u, tau_s=0.9) as s:
                 s.set_populations(to_dev(f0, torch.float64))
@@ -428,9 +430,10 @@ def test_three_step_kernel_equals_single_steps(smrt, storage, boundary, scheme, 
 
 
 @pytest.mark.parametrize("nx,ny", [(3, 3), (5, 70), (13, 21), (64, 64), (65, 9)])
-def test_three_step_kernel_small_cavities(smrt, nx, ny):
+@pytest.mark.parametrize("multi", [3, 4])
+def test_multi_step_kernel_small_cavities(smrt, nx, ny, multi):
     outs = []
-    for spl in (1, 3):
+    for spl in (1, multi):
         with smrt.Solver(nx, ny, scheme="smrt", boundary="cavity", storage="f32", tau=0.6,
                          u_lid=0.1) as s:
             s.set_steps_per_launch(spl, tile_rows=8)
@@ -440,7 +443,8 @@ def test_three_step_kernel_small_cavities(smrt, nx, ny):
 
 
 @pytest.mark.parametrize("boundary", ["periodic", "cavity"])
-def test_three_step_tile_order_does_not_change_results(smrt, boundary):
+@pytest.mark.parametrize("multi", [3, 4])
+def test_multi_step_tile_order_does_not_change_results(smrt, boundary, multi):
     nx, ny, steps = 203, 77, 21
     f0 = inputs.perturbed_populations(nx, ny, eps=0.03, seed=8)
     outs = []
@@ -448,7 +452,7 @@ def test_three_step_tile_order_does_not_change_results(smrt, boundary):
         with smrt.Solver(nx, ny, scheme="smrt", boundary=boundary, storage="f32", tau=0.56,
                          u_lid=0.1 if boundary == "cavity" else 0.0) as s:
             s.set_populations(to_dev(f0, torch.float64))
-            s.set_steps_per_launch(3, tile_rows=16, tile_cols=64)
+            s.set_steps_per_launch(multi, tile_rows=16, tile_cols=64)
             s.set_tile_order(panel)
             s.step(steps)
             outs.append(s.populations(torch.float64).cpu().numpy())
@@ -464,7 +468,11 @@ def test_three_step_kernel_rejects_unsupported(smrt):
         with pytest.raises(smrt.SmrtError):
             s.set_steps_per_launch(3, tile_rows=4)     # tile not offered
         with pytest.raises(smrt.SmrtError):
-            s.set_steps_per_launch(4)
+            s.set_steps_per_launch(4)                  # periodic, nx < 64 + 6
+        with pytest.raises(smrt.SmrtError):
+            s.set_steps_per_launch(5)
+    with smrt.Solver(70, 100, scheme="smrt", boundary="periodic", storage="f32", tau=0.7) as s:
+        s.set_steps_per_launch(4)                      # 70 >= 64 + 6, 100 >= 16 + 6
 
 
 def test_two_step_kernel_against_oracle(smrt):
