@@ -6,11 +6,15 @@
 // step reads one buffer and writes the other: inputs are read-only and each
 // output element has exactly one writer.
 //
-// The stream-collide kernel is a pull scheme: node x gathers d_a(x - e_a) from
-// the previous step, which is the streaming half of Eq. (lb.srt) /
+// The stream-collide kernels are a pull scheme: node x gathers d_a(x - e_a)
+// from the previous step, which is the streaming half of Eq. (lb.srt) /
 // Eq. (SmrtLBM-1), then forms the moments (Eq. fea-0), the equilibrium
-// (Eq. feq-full) and the collision, and writes nine aligned values.  It is
-// bound by HBM traffic: 9 loads and 9 stores per node, about 100 flops.
+// (Eq. feq-full) and the collision, and writes nine aligned values.  One step
+// per launch (stream_collide) is bound by HBM traffic: 9 loads and 9 stores
+// per node, about 70 vector instructions.  The multi-step kernels
+// (stream_collide_x2 .. _x4) keep the intermediate steps of a tile in LDS, so
+// HBM traffic per node-update falls to 1/S and the vector ALU becomes the
+// co-limit.
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -266,13 +266,14 @@ template <typename T> int launch_step(smrt_ctx* c, const void* src, void* dst)
 }
 
 // Threads per two-step workgroup: 512 for tiles of 1024 nodes or more.
-constexpr int x2_threads(int tx, int ty) { return tx * ty >= 1024 ? 512 : 256; }
+// Threads per multi-step workgroup: 512 for tiles of 1024 nodes or more.
+constexpr int multi_threads(int tx, int ty, int steps) { return (void)steps, tx * ty >= 1024 ? 512 : 256; }
 
 template <typename T, int SCHEME, int BC, int TX, int TY, int STEPS>
 int launch_multi(smrt_ctx* c, const T* s, T* d, const smrt::Geom& g,
                  const smrt::Coef<typename smrt::Storage<T>::C>& k, int ntiles)
 {
-    constexpr int NT = x2_threads(TX, TY);
+    constexpr int NT = multi_threads(TX, TY, STEPS);
     if constexpr (STEPS == 4)
         smrt::stream_collide_x4<T, SCHEME, BC, TX, TY, NT><<<ntiles, NT, 0, c->stream>>>(s, d, g, k);
     else if constexpr (STEPS == 3)
@@ -321,51 +322,47 @@ template <typename T, int STEPS, int TX, int TY> int launch_multi_tile(smrt_ctx*
 }
 
 // Two-step tiles offered: 64 x {4, 8, 16, 32} and 128 x {4, 8}.
-template <typename T> int launch_step2(smrt_ctx* c, const void* src, void* dst)
+template <typename T> int launch_step2(smrt_ctx* c, int cols, int rows, const void* src, void* dst)
 {
-    if (c->fused_cols == 128) {
-        if (c->fused_rows == 4) return launch_multi_tile<T, 2, 128, 4>(c, src, dst);
+    if (cols == 128) {
+        if (rows == 4) return launch_multi_tile<T, 2, 128, 4>(c, src, dst);
         return launch_multi_tile<T, 2, 128, 8>(c, src, dst);
     }
-    if (c->fused_rows == 4) return launch_multi_tile<T, 2, 64, 4>(c, src, dst);
-    if (c->fused_rows == 16) return launch_multi_tile<T, 2, 64, 16>(c, src, dst);
-    if (c->fused_rows == 32) return launch_multi_tile<T, 2, 64, 32>(c, src, dst);
-    return launch_multi_tile<T, 2, 64, 8>(c, src, dst);
-}
-
-// Three-step tiles offered: 64 x {8, 16}.
-template <typename T> int launch_step3(smrt_ctx* c, const void* src, void* dst)
-{
-    if (c->fused_rows == 16) return launch_multi_tile<T, 3, 64, 16>(c, src, dst);
-    return launch_multi_tile<T, 3, 64, 8>(c, src, dst);
-}
-
-// Four-step tiles offered: 64 x {8, 16}.
-template <typename T> int launch_step4(smrt_ctx* c, const void* src, void* dst)
-{
-    if (c->fused_rows == 16) return launch_multi_tile<T, 4, 64, 16>(c, src, dst);
-    return launch_multi_tile<T, 4, 64, 8>(c, src, dst);
-}
-
-// Three or four time steps in one launch (FP32 and 16-bit storage only).
-int dispatch_step34(smrt_ctx* c, int k, const void* src, void* dst)
-{
-    switch (c->p.storage) {
-    case SMRT_F32: return k == 4 ? launch_step4<float>(c, src, dst) : launch_step3<float>(c, src, dst);
-    case SMRT_F16: return k == 4 ? launch_step4<_Float16>(c, src, dst) : launch_step3<_Float16>(c, src, dst);
-    case SMRT_BF16: return k == 4 ? launch_step4<smrt::bf16>(c, src, dst) : launch_step3<smrt::bf16>(c, src, dst);
-    default: return fail(SMRT_EINVAL, "multi-step launches need FP32 or 16-bit storage");
+    switch (rows) {
+    case 4: return launch_multi_tile<T, 2, 64, 4>(c, src, dst);
+    case 16: return launch_multi_tile<T, 2, 64, 16>(c, src, dst);
+    case 32: return launch_multi_tile<T, 2, 64, 32>(c, src, dst);
+    default: return launch_multi_tile<T, 2, 64, 8>(c, src, dst);
     }
 }
 
-// Two time steps in one launch (FP32 and 16-bit storage only).
-int dispatch_step2(smrt_ctx* c, const void* src, void* dst)
+// Three- and four-step tiles offered: 64 x {8, 16, 24, 26}.
+template <typename T, int STEPS> int launch_step34(smrt_ctx* c, int rows, const void* src, void* dst)
+{
+    switch (rows) {
+    case 16: return launch_multi_tile<T, STEPS, 64, 16>(c, src, dst);
+    case 24: return launch_multi_tile<T, STEPS, 64, 24>(c, src, dst);
+    case 26: return launch_multi_tile<T, STEPS, 64, 26>(c, src, dst);
+    default: return launch_multi_tile<T, STEPS, 64, 8>(c, src, dst);
+    }
+}
+
+// One launch of k = 2, 3 or 4 time steps with a 64 x rows tile (2: also
+// cols x rows with cols = 128); FP32 and 16-bit storage only.
+template <typename T> int launch_k(smrt_ctx* c, int k, int cols, int rows, const void* src, void* dst)
+{
+    if (k == 4) return launch_step34<T, 4>(c, rows, src, dst);
+    if (k == 3) return launch_step34<T, 3>(c, rows, src, dst);
+    return launch_step2<T>(c, cols, rows, src, dst);
+}
+
+int dispatch_multi(smrt_ctx* c, int k, int cols, int rows, const void* src, void* dst)
 {
     switch (c->p.storage) {
-    case SMRT_F32: return launch_step2<float>(c, src, dst);
-    case SMRT_F16: return launch_step2<_Float16>(c, src, dst);
-    case SMRT_BF16: return launch_step2<smrt::bf16>(c, src, dst);
-    default: return fail(SMRT_EINVAL, "two-step launches need FP32 or 16-bit storage");
+    case SMRT_F32: return launch_k<float>(c, k, cols, rows, src, dst);
+    case SMRT_F16: return launch_k<_Float16>(c, k, cols, rows, src, dst);
+    case SMRT_BF16: return launch_k<smrt::bf16>(c, k, cols, rows, src, dst);
+    default: return fail(SMRT_EINVAL, "multi-step launches need FP32 or 16-bit storage");
     }
 }
 
@@ -473,27 +470,36 @@ int smrt_create(const smrt_params* p, void* dev_ws, size_t ws_bytes, smrt_ctx** 
         // Default block shape: one row segment per block, as wide as the
         // lattice allows (512 measured best on 4096^2, within 1-2% of 256).
         // FP32 and 16-bit storage take the LDS-blocked kernels, tiles in XCD
-        // panels of 8 tile columns.  Measured on 512^2 .. 4096^2 with 64 x 16
-        // tiles (512 threads): FP32 four steps per launch while that gives
-        // >= 256 workgroups, 16-bit storage three steps while it gives >=
+        // panels of 8 tile columns, 512 threads per workgroup.  Measured on
+        // 512^2 .. 4096^2: FP32 four steps per launch, with 64 x 26 tiles
+        // while that gives >= 1024 workgroups (the tall tile leaves fewer
+        // idle lanes on the rings), else 64 x 16 while that gives >= 256;
+        // 16-bit storage three steps with 64 x 16 tiles while that gives >=
         // 1024; smaller lattices two steps with 64 x 32 tiles while that
         // gives >= 512 workgroups, else with 64 x 4.  Periodic lattices need
         // room for the rings.
         if (p->storage != SMRT_F64) {
-            const int64_t cols = (p->nx + 63) / 64, tiles16 = cols * ((p->ny + 15) / 16);
+            const int64_t cols = (p->nx + 63) / 64;
+            const auto tiles = [&](int rows) { return cols * ((p->ny + rows - 1) / rows); };
             const bool per = p->boundary == SMRT_PERIODIC;
-            const int deep = p->storage == SMRT_F32 ? 4 : 3;
-            const int64_t deep_min = p->storage == SMRT_F32 ? 256 : 1024;
-            const int ring = deep - 1;
+            const auto fits = [&](int steps, int rows) {
+                return !per || (p->nx >= 64 + 2 * (steps - 1) && p->ny >= rows + 2 * (steps - 1));
+            };
             c->fused_cols = 64;
             c->panel = 8;
-            if (tiles16 >= deep_min && (!per || (p->nx >= 64 + 2 * ring && p->ny >= 16 + 2 * ring))) {
-                c->fused = deep;
+            if (p->storage == SMRT_F32 && tiles(26) >= 1024 && fits(4, 26)) {
+                c->fused = 4;
+                c->fused_rows = 26;
+            } else if (p->storage == SMRT_F32 && tiles(16) >= 256 && fits(4, 16)) {
+                c->fused = 4;
+                c->fused_rows = 16;
+            } else if (p->storage != SMRT_F32 && tiles(16) >= 1024 && fits(3, 16)) {
+                c->fused = 3;
                 c->fused_rows = 16;
             } else {
-                c->fused_rows = cols * ((p->ny + 31) / 32) >= 512 ? 32 : 4;
+                c->fused_rows = tiles(32) >= 512 ? 32 : 4;
                 if (per && p->ny < c->fused_rows + 2) c->fused_rows = 4;
-                if (!per || (p->nx >= 66 && p->ny >= c->fused_rows + 2)) c->fused = 2;
+                if (fits(2, c->fused_rows)) c->fused = 2;
             }
         }
         if (p->nx >= 512) {
@@ -587,13 +593,20 @@ int smrt_step(smrt_ctx* c, int64_t n)
     if (n < 0) return fail(SMRT_EINVAL, "step count must be >= 0 (got %lld)", (long long)n);
     int64_t left = n;
     while (left > 0) {
-        // the largest launch that fits: fused steps, then fewer with the same
-        // tile (every three- and four-step tile is also a two-step tile)
+        // the largest launch that fits: fused steps, then one shorter launch
+        // (three steps with the same tile; two steps with the same tile, or
+        // 64 x 16 / 64 x 8 after a deeper mode, whose rings need at least as
+        // much room on a periodic lattice)
         const int k = (int)std::min<int64_t>(c->fused, left);
         const void* src = c->buffer(c->cur);
         void* dst = c->buffer(c->cur ^ 1);
-        int rc = k >= 3 ? dispatch_step34(c, k, src, dst)
-                        : k == 2 ? dispatch_step2(c, src, dst) : dispatch_step(c, src, dst);
+        int rc;
+        if (k == 1)
+            rc = dispatch_step(c, src, dst);
+        else if (k == 2 && c->fused > 2)
+            rc = dispatch_multi(c, 2, 64, c->fused_rows >= 16 ? 16 : 8, src, dst);
+        else
+            rc = dispatch_multi(c, k, c->fused_cols, c->fused_rows, src, dst);
         if (rc) return rc;
         c->cur ^= 1;
         c->steps += k;
@@ -677,14 +690,19 @@ int smrt_set_steps_per_launch(smrt_ctx* c, int32_t steps, int32_t tile_cols, int
 {
     if (!c) return fail(SMRT_EINVAL, "context is NULL");
     if (steps < 1 || steps > 4) return fail(SMRT_EINVAL, "steps per launch must be 1 .. 4 (got %d)", steps);
+    if (steps == 1) { // one step per launch has no tile: keep the multi-step one
+        c->fused = 1;
+        return SMRT_OK;
+    }
     if (tile_cols == 0) tile_cols = 64;
     if (tile_rows == 0) tile_rows = steps >= 3 ? 16 : 8;
-    const bool ok = steps >= 3 ? tile_cols == 64 && (tile_rows == 8 || tile_rows == 16)
+    const bool ok = steps >= 3 ? tile_cols == 64 && (tile_rows == 8 || tile_rows == 16 || tile_rows == 24 ||
+                                                     tile_rows == 26)
                                : (tile_cols == 64 && (tile_rows == 4 || tile_rows == 8 || tile_rows == 16 ||
                                                       tile_rows == 32)) ||
                                      (tile_cols == 128 && (tile_rows == 4 || tile_rows == 8));
     if (!ok) return fail(SMRT_EINVAL, "%d-step tile %d x %d not offered", steps, tile_cols, tile_rows);
-    if (steps >= 2) {
+    {
         if (c->p.storage == SMRT_F64) return fail(SMRT_EINVAL, "multi-step launches need FP32 or 16-bit storage");
         // A periodic ring wraps once, which needs the lattice wider than the tile plus its rings.
         const int ring = steps - 1;

@@ -339,7 +339,7 @@ class Solver:
     def set_steps_per_launch(self, steps, tile_rows=0, tile_cols=0):
         """1, or 2 .. 4 for the LDS-blocked kernels (FP32/16-bit storage);
         two-step tiles 64 x {4, 8, 16, 32} or 128 x {4, 8} (0 = 64 x 8),
-        three- and four-step tiles 64 x {8, 16} (0 = 64 x 16)."""
+        three- and four-step tiles 64 x {8, 16, 24, 26} (0 = 64 x 16)."""
         _check(load().smrt_set_steps_per_launch(self._ctx, int(steps), int(tile_cols), int(tile_rows)))
 
     def set_tile_order(self, panel_cols):

@@ -406,7 +406,7 @@ def test_tile_order_does_not_change_results(smrt, boundary, tile):
 @pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
 @pytest.mark.parametrize("boundary", ["periodic", "cavity"])
 @pytest.mark.parametrize("scheme", ["srt", "smrt", "trt"])
-@pytest.mark.parametrize("tile", [(64, 8), (64, 16)])
+@pytest.mark.parametrize("tile", [(64, 8), (64, 16), (64, 26)])
 @pytest.mark.parametrize("multi", [3, 4])
 def test_multi_step_kernel_equals_single_steps(smrt, storage, boundary, scheme, tile, multi):
     """Three or four steps per launch (nested LDS rings, each step written
