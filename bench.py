@@ -148,9 +148,31 @@ def cpu_baseline(args, fields, budget_s):
     f = L.run(f, steps)
     dt = time.perf_counter() - t0
     cells = args.n * args.n * steps
-    return {"value": cells / dt / 1e6, "unit": "MLUPS", "cores": O.get_threads(), "kind": "oracle",
+    threads = O.get_threads()
+    # one-thread rate on the same lattice: one time step
+    O.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        f = L.run(f, 1)
+        dt1 = time.perf_counter() - t0
+    finally:
+        O.set_threads(threads)
+    return {"value": cells / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": "%d time steps of the %dx%d periodic Taylor-Green lattice (%s, tau=%g), "
-                      "FP64, %.1f s" % (steps, args.n, args.n, args.scheme, args.tau, dt)}
+                      "FP64, %.1f s" % (steps, args.n, args.n, args.scheme, args.tau, dt),
+            "value_1_thread": args.n * args.n / dt1 / 1e6, "cpu_model": cpu_model()}
+
+
+def cpu_model():
+    """The host CPU's model name, from /proc/cpuinfo."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cavity_to_steady(args):
