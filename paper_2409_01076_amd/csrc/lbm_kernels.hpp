@@ -138,7 +138,7 @@ struct Geom {
     int64_t plane; // elements per direction plane
     int bx, by, rows;
     int tiles_x;   // tiles along x
-    int panel;     // two-step kernel: tile order, 0 = row-major, P > 0 = XCD panels of P tile columns
+    int panel;     // multi-step kernels: tile order, 0 = row-major, P > 0 = XCD panels of P tile columns
 };
 
 // Workgroups are dealt to the 8 XCDs round-robin.  This renumbering gives
@@ -442,15 +442,12 @@ __global__ void __launch_bounds__(1024) stream_collide(const T* __restrict__ src
     }
 }
 
-// Two time steps per launch (temporal blocking).  A workgroup owns a
-// TX x TY tile of outputs.  Phase 1 computes step t+1 (gather from the
-// previous buffer, collide) on the tile plus a one-node ring and keeps it in
-// LDS; phase 2 pulls from LDS, collides again and stores step t+2.  The HBM
-// traffic per node-update halves (read d(t), write d(t+2)); the ring adds
-// (TX + 2)(TY + 2) / (TX TY) - 1 redundant collisions.  Per node the
+// Several time steps per launch (temporal blocking).  A workgroup owns a
+// TX x TY tile of outputs; the steps before the last are computed on the
+// tile plus a ring of nodes and kept in LDS (multi_tile below).  Per node the
 // arithmetic is that of stream_collide (same gather, collide and, for 16-bit
 // storage, the same rounding to the storage grid between the steps), so the
-// results are bitwise those of two one-step launches.
+// results are bitwise those of one-step launches.
 
 // The first step of a multi-step launch, in two halves over a region of
 // RX x RY nodes: the tile (X0, Y0, TX x TY) plus a ring of RING nodes.

@@ -199,8 +199,8 @@ struct smrt_ctx {
     int64_t steps = 0, snap_step = 0;
     int bx = 256, by = 1, rows = 1;
     int fused = 1;                 // time steps per launch (1, or 2 .. 4 with the LDS-blocked kernels)
-    int fused_cols = 64, fused_rows = 8; // tile of the two-step kernel
-    int panel = 0;                 // two-step kernel: tile order (0 = row-major)
+    int fused_cols = 64, fused_rows = 8; // tile of the multi-step kernels
+    int panel = 0;                 // multi-step kernels: tile order (0 = row-major)
 
     void* buffer(int which) const { return ws + (which == 0 ? L.off_a : L.off_b); }
     double* snap_x() const { return reinterpret_cast<double*>(ws + L.off_snap_x); }
@@ -265,15 +265,14 @@ template <typename T> int launch_step(smrt_ctx* c, const void* src, void* dst)
     return SMRT_OK;
 }
 
-// Threads per two-step workgroup: 512 for tiles of 1024 nodes or more.
 // Threads per multi-step workgroup: 512 for tiles of 1024 nodes or more.
-constexpr int multi_threads(int tx, int ty, int steps) { return (void)steps, tx * ty >= 1024 ? 512 : 256; }
+constexpr int multi_threads(int tx, int ty) { return tx * ty >= 1024 ? 512 : 256; }
 
 template <typename T, int SCHEME, int BC, int TX, int TY, int STEPS>
 int launch_multi(smrt_ctx* c, const T* s, T* d, const smrt::Geom& g,
                  const smrt::Coef<typename smrt::Storage<T>::C>& k, int ntiles)
 {
-    constexpr int NT = multi_threads(TX, TY, STEPS);
+    constexpr int NT = multi_threads(TX, TY);
     if constexpr (STEPS == 4)
         smrt::stream_collide_x4<T, SCHEME, BC, TX, TY, NT><<<ntiles, NT, 0, c->stream>>>(s, d, g, k);
     else if constexpr (STEPS == 3)

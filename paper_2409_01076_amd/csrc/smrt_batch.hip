@@ -218,13 +218,13 @@ int upload_tables(smrt_batch* b)
     return SMRT_OK;
 }
 
-// Threads per two-step workgroup: 512 for 64 x 16 tiles, 256 for smaller.
-constexpr int two_threads(int ty) { return ty >= 16 ? 512 : 256; }
+// Threads per multi-step workgroup: 512 for 64 x 16 tiles, 256 for smaller.
+constexpr int multi_threads(int ty) { return ty >= 16 ? 512 : 256; }
 
 template <typename T, int SCHEME, int TY>
 void launch_two_tile(smrt_batch* b, hipStream_t s, int parity, dim3 grid)
 {
-    constexpr int NT = two_threads(TY);
+    constexpr int NT = multi_threads(TY);
     smrt::batch_stream_collide_x2<T, SCHEME, 64, TY, NT><<<grid, NT, 0, s>>>(
         b->desc(), b->table(), b->ntiles_dev(), reinterpret_cast<T*>(b->state()), parity);
 }
@@ -232,7 +232,7 @@ void launch_two_tile(smrt_batch* b, hipStream_t s, int parity, dim3 grid)
 template <typename T, int SCHEME, int TY>
 void launch_three_tile(smrt_batch* b, hipStream_t s, int parity, dim3 grid)
 {
-    constexpr int NT = two_threads(TY);
+    constexpr int NT = multi_threads(TY);
     smrt::batch_stream_collide_x3<T, SCHEME, 64, TY, NT><<<grid, NT, 0, s>>>(
         b->desc(), b->table(), b->ntiles_dev(), reinterpret_cast<T*>(b->state()), parity);
 }
@@ -240,7 +240,7 @@ void launch_three_tile(smrt_batch* b, hipStream_t s, int parity, dim3 grid)
 template <typename T, int SCHEME, int TY>
 void launch_four_tile(smrt_batch* b, hipStream_t s, int parity, dim3 grid)
 {
-    constexpr int NT = two_threads(TY);
+    constexpr int NT = multi_threads(TY);
     smrt::batch_stream_collide_x4<T, SCHEME, 64, TY, NT><<<grid, NT, 0, s>>>(
         b->desc(), b->table(), b->ntiles_dev(), reinterpret_cast<T*>(b->state()), parity);
 }
@@ -584,7 +584,7 @@ int smrt_batch_autotune(smrt_batch* b, int32_t steps, int32_t* chosen)
         b->multi = multi;
         rc = upload_tables(b);
         if (rc) break;
-        const int per_block_waves = multi > 1 ? two_threads(b->shape.by) / 64 : (b->shape.bx * b->shape.by) / 64;
+        const int per_block_waves = multi > 1 ? multi_threads(b->shape.by) / 64 : (b->shape.bx * b->shape.by) / 64;
         const int grids[] = {b->ntiles, cus * std::max(1, 8 / per_block_waves), cus * std::max(1, 16 / per_block_waves),
                              cus * std::max(1, 32 / per_block_waves)};
         for (int gi = 0; gi < 4; ++gi) {

@@ -475,6 +475,26 @@ def test_three_step_kernel_rejects_unsupported(smrt):
         s.set_steps_per_launch(4)                      # 70 >= 64 + 6, 100 >= 16 + 6
 
 
+@pytest.mark.parametrize("n,boundary,steps", [(4096, "periodic", 402), (1024, "cavity", 4001)])
+def test_default_launch_long_run_bitwise(smrt, n, boundary, steps):
+    """The default launch configuration (four steps per launch, 64 x 26 tiles on
+    4096^2, 64 x 16 on 1024^2) over many launches at the benchmark sizes:
+    populations bitwise those of one step per launch, compared on the device."""
+    outs = []
+    for default in (True, False):
+        with smrt.Solver(n, n, scheme="smrt", boundary=boundary, storage="f32", tau=0.6,
+                         u_lid=0.1 if boundary == "cavity" else 0.0) as s:
+            if boundary == "periodic":
+                s.init_fields(*(to_dev(a) for a in inputs.taylor_green(n, n)))
+            if default:
+                assert s.steps_per_launch == 4
+            else:
+                s.set_steps_per_launch(1)
+            s.step(steps)
+            outs.append(s.populations(torch.float64))  # w + d exactly: distinct d stay distinct
+    assert torch.equal(outs[0], outs[1])
+
+
 def test_two_step_kernel_against_oracle(smrt):
     n, u, steps = 96, 0.1, 600
     with smrt.Solver(n, n, scheme="smrt", boundary="cavity", storage="f32", re=300.0, u_lid=u) as s:
