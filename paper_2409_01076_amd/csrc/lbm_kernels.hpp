@@ -465,7 +465,7 @@ template <typename T, int RX, int RY, int NT> struct RingRegs {
     bool live[P];
 };
 
-template <typename T, int BC, int RX, int RY, int NT, int RING>
+template <typename T, int BC, int RX, int RY, int NT, int RING, bool INNER>
 __device__ __forceinline__ void ring_load(const T* __restrict__ src, const Geom& g, typename Storage<T>::C lid,
                                           int X0, int Y0, RingRegs<T, RX, RY, NT>& r)
 {
@@ -475,6 +475,12 @@ __device__ __forceinline__ void ring_load(const T* __restrict__ src, const Geom&
         const int i = threadIdx.x + j * NT;
         const int lx = i % RX, ly = i / RX;
         const int xu = X0 - RING + lx, yu = Y0 - RING + ly;
+        if constexpr (INNER) {
+            // the whole region lies inside the lattice, off its outer ring
+            r.live[j] = i < RX * RY;
+            if (r.live[j]) gather_interior<T>(pb, g, xu, yu, r.d[j]);
+            continue;
+        }
         int x = xu, y = yu;
         if constexpr (BC == PERIODIC) {
             r.live[j] = i < RX * RY && xu <= g.nx + RING - 1 && yu <= g.ny + RING - 1;
@@ -514,7 +520,7 @@ __device__ __forceinline__ void ring_collide(const Coef<typename Storage<T>::C>&
 // population where the source lies beyond a cavity wall (plus the lid term
 // from the lid row).  Periodic regions hold the wrapped nodes' values, so
 // their pulls need no wrap.
-template <typename T, int BC, int RX, int RY>
+template <typename T, int BC, int RX, int RY, bool INNER = false>
 __device__ __forceinline__ void pull_lds(const typename Storage<T>::C (&m)[9][RY][RX], const Geom& g,
                                          typename Storage<T>::C lid, int lx, int ly, int x, int y,
                                          typename Storage<T>::C d[9])
@@ -522,7 +528,7 @@ __device__ __forceinline__ void pull_lds(const typename Storage<T>::C (&m)[9][RY
     using C = typename Storage<T>::C;
 #pragma unroll
     for (int a = 0; a < 9; ++a) d[a] = m[a][ly - EY[a]][lx - EX[a]];
-    if constexpr (BC == CAVITY) {
+    if constexpr (BC == CAVITY && !INNER) {
         // only lanes on the lattice's outer ring have sources beyond a wall
         if ((x == 0) | (x == g.nx - 1) | (y == 0) | (y == g.ny - 1)) {
 #pragma unroll
@@ -538,7 +544,7 @@ __device__ __forceinline__ void pull_lds(const typename Storage<T>::C (&m)[9][RY
 
 // Last step of a multi-step launch: pull the previous step from LDS (held on
 // the tile plus a one-node ring), collide, store to HBM.
-template <typename T, int SCHEME, int BC, int TX, int TY, int NT>
+template <typename T, int SCHEME, int BC, int TX, int TY, int NT, bool INNER = false>
 __device__ __forceinline__ void lds_to_hbm(T* __restrict__ dst, const Geom& g, const Coef<typename Storage<T>::C>& k,
                                            int X0, int Y0, const typename Storage<T>::C (&m)[9][TY + 2][TX + 2])
 {
@@ -547,9 +553,9 @@ __device__ __forceinline__ void lds_to_hbm(T* __restrict__ dst, const Geom& g, c
     for (int i = threadIdx.x; i < TX * TY; i += NT) {
         const int tx = i % TX, ty = i / TX;
         const int x = X0 + tx, y = Y0 + ty;
-        if (x >= g.nx || y >= g.ny) continue;
+        if (!INNER && (x >= g.nx || y >= g.ny)) continue;
         C d[9];
-        pull_lds<T, BC, TX + 2, TY + 2>(m, g, k.lid, tx + 1, ty + 1, x, y, d);
+        pull_lds<T, BC, TX + 2, TY + 2, INNER>(m, g, k.lid, tx + 1, ty + 1, x, y, d);
         collide<SCHEME, T>(d, k);
         scatter_store<T>(sb, g, x, y, d);
     }
@@ -588,7 +594,7 @@ template <typename T, int TX, int TY, int S> struct MultiTile {
 
 // A middle step: pull from the ring-(r+1) step in LDS, collide on the tile
 // plus a ring of r nodes, then (after every pull is done) write over the LDS.
-template <typename T, int SCHEME, int BC, int TX, int TY, int NT, int S, int r>
+template <typename T, int SCHEME, int BC, int TX, int TY, int NT, int S, int r, bool INNER>
 __device__ __forceinline__ void middle_step(const Geom& g, const Coef<typename Storage<T>::C>& k, int X0, int Y0,
                                             MultiTile<T, TX, TY, S>& sh)
 {
@@ -602,12 +608,14 @@ __device__ __forceinline__ void middle_step(const Geom& g, const Coef<typename S
         const int i = threadIdx.x + j * NT;
         const int lx = i % BX, ly = i / BX;
         const int x = X0 - r + lx, y = Y0 - r + ly; // unwrapped
-        if constexpr (BC == PERIODIC)
+        if constexpr (INNER)
+            live[j] = i < BX * BY;
+        else if constexpr (BC == PERIODIC)
             live[j] = i < BX * BY && x <= g.nx + r - 1 && y <= g.ny + r - 1;
         else
             live[j] = i < BX * BY && (unsigned)x < (unsigned)g.nx && (unsigned)y < (unsigned)g.ny;
         if (live[j]) {
-            pull_lds<T, BC, AX, AY>(sh.template ring<r + 1>(), g, k.lid, lx + 1, ly + 1, x, y, d[j]);
+            pull_lds<T, BC, AX, AY, INNER>(sh.template ring<r + 1>(), g, k.lid, lx + 1, ly + 1, x, y, d[j]);
             collide<SCHEME, T>(d[j], k);
             if constexpr (Storage<T>::kRounds) d[j][0] = Storage<T>::stored_value(d[j][0], 0);
         }
@@ -625,21 +633,38 @@ __device__ __forceinline__ void middle_step(const Geom& g, const Coef<typename S
     __syncthreads();
 }
 
+template <typename T, int SCHEME, int BC, int TX, int TY, int NT, int S, bool INNER>
+__device__ __forceinline__ void multi_tile_body(const T* __restrict__ src, T* __restrict__ dst, const Geom& g,
+                                                const Coef<typename Storage<T>::C>& k, int X0, int Y0,
+                                                MultiTile<T, TX, TY, S>& sh)
+{
+    constexpr int R = S - 1;
+    {
+        RingRegs<T, TX + 2 * R, TY + 2 * R, NT> r;
+        ring_load<T, BC, TX + 2 * R, TY + 2 * R, NT, R, INNER>(src, g, k.lid, X0, Y0, r);
+        ring_collide<T, SCHEME, TX + 2 * R, TY + 2 * R, NT>(k, r, sh.template ring<R>());
+    }
+    __syncthreads();
+    if constexpr (R >= 3) middle_step<T, SCHEME, BC, TX, TY, NT, S, 2, INNER>(g, k, X0, Y0, sh);
+    if constexpr (R >= 2) middle_step<T, SCHEME, BC, TX, TY, NT, S, 1, INNER>(g, k, X0, Y0, sh);
+    lds_to_hbm<T, SCHEME, BC, TX, TY, NT, INNER>(dst, g, k, X0, Y0, sh.template ring<1>());
+}
+
+// A tile whose widest region (the tile plus S - 1 rings) lies inside the
+// lattice, off its outer ring, needs no wrap, bounce-back or bounds checks:
+// most tiles of a large lattice take that copy of the code (same
+// arithmetic, so the same results).
 template <typename T, int SCHEME, int BC, int TX, int TY, int NT, int S>
 __device__ __forceinline__ void multi_tile(const T* __restrict__ src, T* __restrict__ dst, const Geom& g,
                                            const Coef<typename Storage<T>::C>& k, int X0, int Y0,
                                            MultiTile<T, TX, TY, S>& sh)
 {
     constexpr int R = S - 1;
-    {
-        RingRegs<T, TX + 2 * R, TY + 2 * R, NT> r;
-        ring_load<T, BC, TX + 2 * R, TY + 2 * R, NT, R>(src, g, k.lid, X0, Y0, r);
-        ring_collide<T, SCHEME, TX + 2 * R, TY + 2 * R, NT>(k, r, sh.template ring<R>());
-    }
-    __syncthreads();
-    if constexpr (R >= 3) middle_step<T, SCHEME, BC, TX, TY, NT, S, 2>(g, k, X0, Y0, sh);
-    if constexpr (R >= 2) middle_step<T, SCHEME, BC, TX, TY, NT, S, 1>(g, k, X0, Y0, sh);
-    lds_to_hbm<T, SCHEME, BC, TX, TY, NT>(dst, g, k, X0, Y0, sh.template ring<1>());
+    const bool inner = X0 - R >= 1 && X0 + TX + R <= g.nx - 1 && Y0 - R >= 1 && Y0 + TY + R <= g.ny - 1;
+    if (inner)
+        multi_tile_body<T, SCHEME, BC, TX, TY, NT, S, true>(src, dst, g, k, X0, Y0, sh);
+    else
+        multi_tile_body<T, SCHEME, BC, TX, TY, NT, S, false>(src, dst, g, k, X0, Y0, sh);
 }
 
 template <typename T, int SCHEME, int BC, int TX, int TY, int NT>
