@@ -568,6 +568,9 @@ def main():
         "mass_drift": mass / mass0 - 1.0,
     }
     out["roofline"]["frac_of_copy_kernel"] = round(achieved / out["copy_kernel_gbs"], 4)
+    # the HBM rate one step per launch would need for the same node updates:
+    # temporal blocking moves 18 s / spl bytes per node-update instead of 18 s
+    out["roofline"]["one_step_equivalent_gbs"] = round(achieved * spl, 1)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, fields, args.cpu_seconds)
     print(json.dumps(out), flush=True)

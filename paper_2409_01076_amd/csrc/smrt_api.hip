@@ -355,13 +355,23 @@ template <typename T> int launch_k(smrt_ctx* c, int k, int cols, int rows, const
     return launch_step2<T>(c, cols, rows, src, dst);
 }
 
+// FP64 storage: twice the LDS per node, so only 64 x 4 and 64 x 8 tiles for
+// two steps and 64 x 8 for three and four.
+int launch_k_f64(smrt_ctx* c, int k, int rows, const void* src, void* dst)
+{
+    if (k == 4) return launch_multi_tile<double, 4, 64, 8>(c, src, dst);
+    if (k == 3) return launch_multi_tile<double, 3, 64, 8>(c, src, dst);
+    if (rows == 4) return launch_multi_tile<double, 2, 64, 4>(c, src, dst);
+    return launch_multi_tile<double, 2, 64, 8>(c, src, dst);
+}
+
 int dispatch_multi(smrt_ctx* c, int k, int cols, int rows, const void* src, void* dst)
 {
     switch (c->p.storage) {
+    case SMRT_F64: return launch_k_f64(c, k, rows, src, dst);
     case SMRT_F32: return launch_k<float>(c, k, cols, rows, src, dst);
     case SMRT_F16: return launch_k<_Float16>(c, k, cols, rows, src, dst);
-    case SMRT_BF16: return launch_k<smrt::bf16>(c, k, cols, rows, src, dst);
-    default: return fail(SMRT_EINVAL, "multi-step launches need FP32 or 16-bit storage");
+    default: return launch_k<smrt::bf16>(c, k, cols, rows, src, dst);
     }
 }
 
@@ -477,7 +487,14 @@ int smrt_create(const smrt_params* p, void* dev_ws, size_t ws_bytes, smrt_ctx** 
         // 1024; smaller lattices two steps with 64 x 32 tiles while that
         // gives >= 512 workgroups, else with 64 x 4.  Periodic lattices need
         // room for the rings.
-        if (p->storage != SMRT_F64) {
+        if (p->storage == SMRT_F64) {
+            // FP64 (twice the LDS per node): four steps with 64 x 8 tiles,
+            // measured best on 512^2 .. 4096^2 (2.5x one step on 4096^2).
+            c->fused_cols = 64;
+            c->fused_rows = 8;
+            c->panel = 8;
+            if (p->boundary == SMRT_CAVITY || (p->nx >= 70 && p->ny >= 14)) c->fused = 4;
+        } else {
             const int64_t cols = (p->nx + 63) / 64;
             const auto tiles = [&](int rows) { return cols * ((p->ny + rows - 1) / rows); };
             const bool per = p->boundary == SMRT_PERIODIC;
@@ -603,7 +620,7 @@ int smrt_step(smrt_ctx* c, int64_t n)
         if (k == 1)
             rc = dispatch_step(c, src, dst);
         else if (k == 2 && c->fused > 2)
-            rc = dispatch_multi(c, 2, 64, c->fused_rows >= 16 ? 16 : 8, src, dst);
+            rc = dispatch_multi(c, 2, 64, c->fused_rows >= 16 ? 16 : 8, src, dst); // FP64: 64 x 8
         else
             rc = dispatch_multi(c, k, c->fused_cols, c->fused_rows, src, dst);
         if (rc) return rc;
@@ -694,15 +711,16 @@ int smrt_set_steps_per_launch(smrt_ctx* c, int32_t steps, int32_t tile_cols, int
         return SMRT_OK;
     }
     if (tile_cols == 0) tile_cols = 64;
-    if (tile_rows == 0) tile_rows = steps >= 3 ? 16 : 8;
-    const bool ok = steps >= 3 ? tile_cols == 64 && (tile_rows == 8 || tile_rows == 16 || tile_rows == 24 ||
-                                                     tile_rows == 26)
-                               : (tile_cols == 64 && (tile_rows == 4 || tile_rows == 8 || tile_rows == 16 ||
-                                                      tile_rows == 32)) ||
-                                     (tile_cols == 128 && (tile_rows == 4 || tile_rows == 8));
+    if (tile_rows == 0) tile_rows = steps >= 3 && c->p.storage != SMRT_F64 ? 16 : 8;
+    bool ok;
+    if (c->p.storage == SMRT_F64)
+        ok = tile_cols == 64 && (tile_rows == 8 || (steps == 2 && tile_rows == 4));
+    else
+        ok = steps >= 3 ? tile_cols == 64 && (tile_rows == 8 || tile_rows == 16 || tile_rows == 24 || tile_rows == 26)
+                        : (tile_cols == 64 && (tile_rows == 4 || tile_rows == 8 || tile_rows == 16 || tile_rows == 32)) ||
+                              (tile_cols == 128 && (tile_rows == 4 || tile_rows == 8));
     if (!ok) return fail(SMRT_EINVAL, "%d-step tile %d x %d not offered", steps, tile_cols, tile_rows);
     {
-        if (c->p.storage == SMRT_F64) return fail(SMRT_EINVAL, "multi-step launches need FP32 or 16-bit storage");
         // A periodic ring wraps once, which needs the lattice wider than the tile plus its rings.
         const int ring = steps - 1;
         if (c->p.boundary == SMRT_PERIODIC && (c->p.nx < tile_cols + 2 * ring || c->p.ny < tile_rows + 2 * ring))

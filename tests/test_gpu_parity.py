@@ -403,6 +403,26 @@ def test_tile_order_does_not_change_results(smrt, boundary, tile):
         assert np.array_equal(outs[0], o)
 
 
+@pytest.mark.parametrize("boundary", ["periodic", "cavity"])
+@pytest.mark.parametrize("scheme", ["srt", "smrt", "trt"])
+@pytest.mark.parametrize("multi,tile", [(2, (64, 4)), (2, (64, 8)), (3, (64, 8)), (4, (64, 8))])
+def test_multi_step_kernel_fp64_equals_single_steps(smrt, boundary, scheme, multi, tile):
+    """FP64 storage (64 x 4 and 64 x 8 tiles): bitwise equal to one-step launches."""
+    nx, ny = 203, 77
+    f0 = inputs.perturbed_populations(nx, ny, eps=0.03, seed=9)
+    u = 0.1 if boundary == "cavity" else 0.0
+    for steps in (41, 43):
+        outs = []
+        for spl in (1, multi):
+            with smrt.Solver(nx, ny, scheme=scheme, boundary=boundary, storage="f64", tau=0.56,
+                             u_lid=u, tau_s=0.9) as s:
+                s.set_populations(to_dev(f0, torch.float64))
+                s.set_steps_per_launch(spl, tile_rows=tile[1], tile_cols=tile[0])
+                s.step(steps)
+                outs.append(s.populations(torch.float64).cpu().numpy())
+        assert np.array_equal(outs[0], outs[1])
+
+
 @pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
 @pytest.mark.parametrize("boundary", ["periodic", "cavity"])
 @pytest.mark.parametrize("scheme", ["srt", "smrt", "trt"])
@@ -431,10 +451,11 @@ def test_multi_step_kernel_equals_single_steps(smrt, storage, boundary, scheme, 
 
 @pytest.mark.parametrize("nx,ny", [(3, 3), (5, 70), (13, 21), (64, 64), (65, 9)])
 @pytest.mark.parametrize("multi", [3, 4])
-def test_multi_step_kernel_small_cavities(smrt, nx, ny, multi):
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_multi_step_kernel_small_cavities(smrt, nx, ny, multi, storage):
     outs = []
     for spl in (1, multi):
-        with smrt.Solver(nx, ny, scheme="smrt", boundary="cavity", storage="f32", tau=0.6,
+        with smrt.Solver(nx, ny, scheme="smrt", boundary="cavity", storage=storage, tau=0.6,
                          u_lid=0.1) as s:
             s.set_steps_per_launch(spl, tile_rows=8)
             s.step(31)
@@ -515,7 +536,9 @@ def test_two_step_kernel_rejects_unsupported(smrt):
         with pytest.raises(smrt.SmrtError):
             s.set_tile_order(-1)
     with smrt.Solver(128, 128, scheme="smrt", boundary="cavity", storage="f64", tau=0.7, u_lid=0.1) as s:
+        s.set_steps_per_launch(2)              # FP64: 64 x 8 tiles
         with pytest.raises(smrt.SmrtError):
-            s.set_steps_per_launch(2)          # FP64 storage
+            s.set_steps_per_launch(2, tile_rows=16)   # FP64: tile not offered
+        s.set_steps_per_launch(4)                      # FP64: 64 x 8 tiles
         with pytest.raises(smrt.SmrtError):
-            s.set_steps_per_launch(3)
+            s.set_steps_per_launch(5)
