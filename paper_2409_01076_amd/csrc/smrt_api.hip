@@ -479,7 +479,7 @@ int smrt_create(const smrt_params* p, void* dev_ws, size_t ws_bytes, smrt_ctx** 
         // Default block shape: one row segment per block, as wide as the
         // lattice allows (512 measured best on 4096^2, within 1-2% of 256).
         // FP32 and 16-bit storage take the LDS-blocked kernels, tiles in XCD
-        // panels of 8 tile columns, 512 threads per workgroup.  Measured on
+        // panels of 16 tile columns, 512 threads per workgroup.  Measured on
         // 512^2 .. 4096^2: FP32 four steps per launch, with 64 x 26 tiles
         // while that gives >= 1024 workgroups (the tall tile leaves fewer
         // idle lanes on the rings), else 64 x 16 while that gives >= 256;
@@ -489,10 +489,11 @@ int smrt_create(const smrt_params* p, void* dev_ws, size_t ws_bytes, smrt_ctx** 
         // room for the rings.
         if (p->storage == SMRT_F64) {
             // FP64 (twice the LDS per node): four steps with 64 x 8 tiles,
-            // measured best on 512^2 .. 4096^2 (2.5x one step on 4096^2).
+            // measured best on 512^2 .. 4096^2 (2.5x one step on 4096^2), in
+            // XCD panels of 32 tile columns (17 % faster than 8 on 4096^2).
             c->fused_cols = 64;
             c->fused_rows = 8;
-            c->panel = 8;
+            c->panel = 32;
             if (p->boundary == SMRT_CAVITY || (p->nx >= 70 && p->ny >= 14)) c->fused = 4;
         } else {
             const int64_t cols = (p->nx + 63) / 64;
@@ -502,7 +503,7 @@ int smrt_create(const smrt_params* p, void* dev_ws, size_t ws_bytes, smrt_ctx** 
                 return !per || (p->nx >= 64 + 2 * (steps - 1) && p->ny >= rows + 2 * (steps - 1));
             };
             c->fused_cols = 64;
-            c->panel = 8;
+            c->panel = 16;
             if (p->storage == SMRT_F32 && tiles(26) >= 1024 && fits(4, 26)) {
                 c->fused = 4;
                 c->fused_rows = 26;
