@@ -68,7 +68,7 @@ def parse():
                          "warmstart: learned warm start against the cold start")
     ap.add_argument("--train", type=int, default=200, help="warmstart: training cavities")
     ap.add_argument("--held-out", type=int, default=50, help="warmstart: evaluation cavities")
-    ap.add_argument("--epochs", type=int, default=30, help="warmstart: training epochs")
+    ap.add_argument("--epochs", type=int, default=120, help="warmstart: training epochs")
     ap.add_argument("--count", type=int, default=256, help="batch: number of cavities")
     ap.add_argument("--schedule", default="",
                     help="cavity: precision schedule 'f16:1e-5' = run in that storage until the "
