@@ -32,11 +32,11 @@ struct MlpLayout {
     std::vector<int> in, out, in_real, out_real; // padded and real sizes per layer
     std::vector<size_t> w_off, b_off;             // offsets (floats) in the padded parameter block
     size_t padded_params = 0, real_params = 0;
-    int max_splits = 64, chunks = 0;
+    int max_splits = 512;
     // byte offsets in the workspace
     size_t off_params = 0, off_wbf = 0, off_grad = 0, off_m = 0, off_v = 0, off_fourier = 0, off_x0 = 0,
            off_z = 0, off_a = 0, off_c = 0, off_y = 0, off_dy = 0, off_dz0 = 0, off_dz1 = 0, off_wpart = 0,
-           off_bpart = 0, off_loss = 0, total = 0;
+           off_red0 = 0, off_red1 = 0, off_loss = 0, total = 0;
     size_t z_stride = 0, a_stride = 0; // elements between hidden layers' Z / A arrays
     int loss_blocks = 0;
 };
@@ -81,7 +81,6 @@ int make_layout(const smrt_mlp_params* p, MlpLayout* out)
     L.padded_params = pp;
     L.real_params = rp;
     const size_t mb = (size_t)L.max_batch;
-    L.chunks = (int)((mb + 255) / 256);
     L.loss_blocks = 1024;
     const int hidden = L.layers - 1;
     L.z_stride = mb * L.width;
@@ -107,7 +106,11 @@ int make_layout(const smrt_mlp_params* p, MlpLayout* out)
     L.off_dz0 = take(mb * L.width * 2);
     L.off_dz1 = take(mb * L.width * 2);
     L.off_wpart = take((size_t)L.max_splits * max_w * 4);
-    L.off_bpart = take((size_t)L.chunks * std::max(L.width, L.n_last) * 4);
+    // column-sum passes: 16-row chunk sums of the split partials or of dZ
+    const size_t red = std::max((size_t)(L.max_splits + 15) / 16 * max_w,
+                                (mb + 15) / 16 * (size_t)std::max(L.width, L.n_last));
+    L.off_red0 = take(red * 4);
+    L.off_red1 = take(red * 4);
     L.off_loss = take((size_t)L.loss_blocks * 8);
     L.total = off;
     *out = std::move(L);
@@ -139,7 +142,7 @@ struct smrt_mlp {
     uint16_t* dy() const { return reinterpret_cast<uint16_t*>(ws + L.off_dy); }
     uint16_t* dz(int i) const { return reinterpret_cast<uint16_t*>(ws + (i ? L.off_dz1 : L.off_dz0)); }
     float* wpart() const { return reinterpret_cast<float*>(ws + L.off_wpart); }
-    float* bpart() const { return reinterpret_cast<float*>(ws + L.off_bpart); }
+    float* red(int i) const { return reinterpret_cast<float*>(ws + (i ? L.off_red1 : L.off_red0)); }
     double* loss_part() const { return reinterpret_cast<double*>(ws + L.off_loss); }
 };
 
@@ -196,11 +199,44 @@ int forward(smrt_mlp* m, const float* pts, int n, float* out)
     return SMRT_OK;
 }
 
+// Row splits of the weight-gradient products: as many as keep >= 128 rows
+// (four K-steps) per split, at most 512, so a 128 x 128 gradient of 65,536
+// rows runs 2048 workgroups.
 int splits_for(int n)
 {
-    int s = 64;
-    while (s > 1 && (n % (32 * s) || n / s < 256)) s >>= 1;
+    int s = 512;
+    while (s > 1 && (n % (32 * s) || n / s < 128)) s >>= 1;
     return s;
+}
+
+// Column sums of a rows x cols array (row stride ld) into out[cols], in a
+// fixed order: passes of 16-row chunk sums (the first pass with longer
+// chunks when rows / 16 would exceed the grid) until at most 16 rows remain,
+// then one pass of plain sums.
+template <typename T>
+void reduce_columns(smrt_mlp* m, hipStream_t s, const T* in, int rows, int cols, int64_t ld, float* out)
+{
+    constexpr int R = 16;
+    const int bx = (cols + 255) / 256;
+    if (rows <= R) {
+        smrt::mlp::column_sums<T><<<bx, 256, 0, s>>>(in, rows, cols, ld, out);
+        return;
+    }
+    const int r1 = std::max(R, (rows + 65534) / 65535); // keeps the grid's y dimension <= 65535
+    int chunks = (rows + r1 - 1) / r1;
+    smrt::mlp::column_sums_chunked<T><<<dim3(bx, chunks), 256, 0, s>>>(in, rows, cols, ld, r1, m->red(0));
+    const float* cur = m->red(0);
+    int which = 1;
+    rows = chunks;
+    while (rows > R) {
+        chunks = (rows + R - 1) / R;
+        smrt::mlp::column_sums_chunked<float><<<dim3(bx, chunks), 256, 0, s>>>(cur, rows, cols, cols, R,
+                                                                              m->red(which));
+        cur = m->red(which);
+        which ^= 1;
+        rows = chunks;
+    }
+    smrt::mlp::column_sums<float><<<bx, 256, 0, s>>>(cur, rows, cols, cols, out);
 }
 
 // Backward pass after forward() wrote m->y(): fills m->grad() (padded layout)
@@ -222,14 +258,9 @@ int backward(smrt_mlp* m, const float* target, int n, double* loss)
         // dW_l = in^T dZ_l, split over the rows, then summed in split order
         rc = gemm(s, true, false, in, dcur, m->wpart(), K, N, n, K, N, N, splits);
         if (rc) return rc;
-        smrt::mlp::column_sums<float><<<(K * N + 255) / 256, 256, 0, s>>>(m->wpart(), splits, K * N, (int64_t)K * N,
-                                                                         m->grad() + L.w_off[l]);
+        reduce_columns<float>(m, s, m->wpart(), splits, K * N, (int64_t)K * N, m->grad() + L.w_off[l]);
         // db_l = column sums of dZ_l
-        const int chunks = (n + 255) / 256;
-        smrt::mlp::column_sums_chunked<uint16_t><<<dim3((N + 255) / 256, chunks), 256, 0, s>>>(dcur, n, N, N, 256,
-                                                                                             m->bpart());
-        smrt::mlp::column_sums<float><<<(N + 255) / 256, 256, 0, s>>>(m->bpart(), chunks, N, N,
-                                                                     m->grad() + L.b_off[l]);
+        reduce_columns<uint16_t>(m, s, dcur, n, N, N, m->grad() + L.b_off[l]);
         rc = after_launch("weight gradients");
         if (rc) return rc;
         if (l == 0) break;

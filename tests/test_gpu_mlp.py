@@ -49,10 +49,10 @@ def test_forward_matches_oracle(smrt):
     assert rel < 2e-2
 
 
-def test_gradient_matches_oracle(smrt):
+@pytest.mark.parametrize("n", [1024, 65536])   # 8 and 512 row splits of the weight gradients
+def test_gradient_matches_oracle(smrt, n):
     rng = np.random.default_rng(2)
     dims, params, B = make_net(rng)
-    n = 1024
     pts = rng.uniform(0, 1, size=(n, 3)).astype(np.float32)
     tgt = rng.normal(0, 0.5, size=(n, 3)).astype(np.float32)
     with smrt.MLP(max_batch=n) as net:
