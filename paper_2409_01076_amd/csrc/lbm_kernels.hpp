@@ -217,32 +217,39 @@ __device__ __forceinline__ void collide(C d[9], const Coef<C>& k)
     const C jy = m24 + (m57 + m68); // e_y = +1 for 2, 5, 6 and -1 for 4, 7, 8
     const C inv = reciprocal(C(1) + drho);
     const C ux = jx * inv, uy = jy * inv;
-    const C jxux = jx * ux, jyuy = jy * uy;
-    const C base = drho - C(1.5) * (jxux + jyuy);
+    // j.u splits into j_x u_x + j_y u_y; on the diagonals (e.j)(e.u) is
+    // j.u + 2 j_x u_y (links 5, 7) or j.u - 2 j_x u_y (links 6, 8), since
+    // j_x u_y = j_y u_x.
+    const C jxux = jx * ux, jyuy = jy * uy, jxuy = jx * uy;
+    const C ju = jxux + jyuy;
+    const C base = drho - C(1.5) * ju;
 
-    const C e5j = jx + jy, e5u = ux + uy; // e_5 = (1, 1) = -e_7
-    const C e6j = jy - jx, e6u = uy - ux; // e_6 = (-1, 1) = -e_8
-    // s = w (base + 9/2 (e.j)(e.u)), with w base formed once per class
-    const C abase = W<C>::axis * base, dbase = W<C>::diag * base;
-    const C sx = abase + (C(4.5) * W<C>::axis) * jxux;
-    const C sy = abase + (C(4.5) * W<C>::axis) * jyuy;
-    const C s5 = dbase + (C(4.5) * W<C>::diag) * (e5j * e5u);
-    const C s6 = dbase + (C(4.5) * W<C>::diag) * (e6j * e6u);
+    // s = w (base + 9/2 (e.j)(e.u)): 9/2 w_axis = 1/2, 9/2 w_diag = 1/8
+    const C abase = W<C>::axis * base;
+    const C dmid = W<C>::diag * base + C(0.125) * ju;
+    const C sx = abase + C(0.5) * jxux;
+    const C sy = abase + C(0.5) * jyuy;
+    const C s5 = dmid + C(0.25) * jxuy;
+    const C s6 = dmid - C(0.25) * jxuy;
+    const C e5j = jx + jy; // e_5 = (1, 1) = -e_7
+    const C e6j = jy - jx; // e_6 = (-1, 1) = -e_8
     const C t5 = C(1.0 / 12.0) * e5j; // 3 w_diag (e_5 . j)
     const C t6 = C(1.0 / 12.0) * e6j;
     const C tx = C(0.5) * jx - (t5 - t6);
     const C ty = C(0.5) * jy - (t5 + t6);
 
+    // Group sums of Eq. (sigma1-2-0), times 4: C_1 over the axis links, C_2
+    // over the diagonal links, each sum_k (-1)^k (f_k - f^eq_k).  The odd
+    // parts cancel in the equilibrium's share, which leaves
+    // q_2 + q_4 - q_1 - q_3 = 2 (s_y - s_x) = j_y u_y - j_x u_x and
+    // q_6 + q_8 - q_5 - q_7 = 2 (s_6 - s_5) = -j_x u_y.
+    const C c1x4 = (p24 - p13) - (jyuy - jxux);
+    const C c2x4 = (p68 - p57) + jxuy;
     if constexpr (SCHEME == SMRT) {
-        // Group sums of Eq. (sigma1-2-0): C_1 over the axis links, C_2 over the
-        // diagonal links, each sum_k (-1)^k (f_k - f^eq_k) / 4; the odd parts
-        // cancel in the equilibrium's share (q_2 + q_4 - q_1 - q_3 = 2 (s_y -
-        // s_x), q_6 + q_8 - q_5 - q_7 = 2 (s_6 - s_5)).
-        const C c1 = C(0.25) * (p24 - p13) - C(0.5) * (sy - sx);
-        const C c2 = C(0.25) * (p68 - p57) - C(0.5) * (s6 - s5);
         // Eq. (SmrtLBM-1): f*_a = f^eq_a + (-1)^a (1 - 1/tau) C_g(a); both
         // members of an opposite pair get the same correction.
-        const C g1 = k.a * c1, g2 = k.a * c2;
+        const C qa = C(0.25) * k.a;
+        const C g1 = qa * c1x4, g2 = qa * c2x4;
         const C ax = sx - g1, ay = sy + g1, a5 = s5 - g2, a6 = s6 + g2;
         d[1] = ax + tx;
         d[3] = ax - tx;
@@ -269,9 +276,8 @@ __device__ __forceinline__ void collide(C d[9], const Coef<C>& k)
             for (int a = 0; a < 9; ++a) d[a] = d[a] + k.omega * (q[a] - d[a]);
         } else {
             // Eq. (SmrtLBM-lb.1.5): f*_a = f_a - (f_a - f^eq_a)/tau_s + (-1)^a (1/tau_s - 1/tau) C_g(a)
-            const C c1 = C(0.25) * (p24 - p13) - C(0.5) * (sy - sx);
-            const C c2 = C(0.25) * (p68 - p57) - C(0.5) * (s6 - s5);
-            const C g1 = k.b * c1, g2 = k.b * c2;
+            const C qb = C(0.25) * k.b;
+            const C g1 = qb * c1x4, g2 = qb * c2x4;
 #pragma unroll
             for (int a = 0; a < 9; ++a) d[a] = d[a] + k.omega_s * (q[a] - d[a]);
             d[1] -= g1;
@@ -515,19 +521,22 @@ __device__ __forceinline__ void ring_collide(const Coef<typename Storage<T>::C>&
     }
 }
 
-// Pull of node (x, y) of the lattice from a step held in LDS as m[9][RY][RX],
-// the node at local (lx, ly): bounce-back from the node's own opposite
-// population where the source lies beyond a cavity wall (plus the lid term
-// from the lid row).  Periodic regions hold the wrapped nodes' values, so
-// their pulls need no wrap.
-template <typename T, int BC, int RX, int RY, bool INNER = false>
-__device__ __forceinline__ void pull_lds(const typename Storage<T>::C (&m)[9][RY][RX], const Geom& g,
-                                         typename Storage<T>::C lid, int lx, int ly, int x, int y,
+// Pull of node (x, y) of the lattice from a step held in LDS as m[9][FY][FX],
+// the node at frame position (fx, fy): bounce-back from the node's own
+// opposite population where the source lies beyond a cavity wall (plus the
+// lid term from the lid row).  Periodic regions hold the wrapped nodes'
+// values, so their pulls need no wrap.  Every source is a constant offset
+// from the node's own cell.
+template <typename T, int BC, int FX, int FY, bool INNER = false>
+__device__ __forceinline__ void pull_lds(const typename Storage<T>::C (&m)[9][FY][FX], const Geom& g,
+                                         typename Storage<T>::C lid, int fx, int fy, int x, int y,
                                          typename Storage<T>::C d[9])
 {
     using C = typename Storage<T>::C;
+    constexpr int PL = FX * FY;
+    const C* own = &m[0][fy][fx];
 #pragma unroll
-    for (int a = 0; a < 9; ++a) d[a] = m[a][ly - EY[a]][lx - EX[a]];
+    for (int a = 0; a < 9; ++a) d[a] = own[a * PL - EY[a] * FX - EX[a]];
     if constexpr (BC == CAVITY && !INNER) {
         // only lanes on the lattice's outer ring have sources beyond a wall
         if ((x == 0) | (x == g.nx - 1) | (y == 0) | (y == g.ny - 1)) {
@@ -535,18 +544,20 @@ __device__ __forceinline__ void pull_lds(const typename Storage<T>::C (&m)[9][RY
             for (int a = 1; a < 9; ++a) {
                 const int sx = x - EX[a], sy = y - EY[a];
                 const bool inside = (unsigned)sx < (unsigned)g.nx && (unsigned)sy < (unsigned)g.ny;
-                const C own = m[OPP[a]][ly][lx];
-                d[a] = inside ? d[a] : ((sy == g.ny) ? own + C(EX[a]) * lid : own);
+                const C back = own[OPP[a] * PL];
+                d[a] = inside ? d[a] : ((sy == g.ny) ? back + C(EX[a]) * lid : back);
             }
         }
     }
 }
 
 // Last step of a multi-step launch: pull the previous step from LDS (held on
-// the tile plus a one-node ring), collide, store to HBM.
-template <typename T, int SCHEME, int BC, int TX, int TY, int NT, bool INNER = false>
+// the tile plus a one-node ring, inside a frame of the tile plus R rings),
+// collide, store to HBM.
+template <typename T, int SCHEME, int BC, int TX, int TY, int NT, int R, bool INNER = false>
 __device__ __forceinline__ void lds_to_hbm(T* __restrict__ dst, const Geom& g, const Coef<typename Storage<T>::C>& k,
-                                           int X0, int Y0, const typename Storage<T>::C (&m)[9][TY + 2][TX + 2])
+                                           int X0, int Y0,
+                                           const typename Storage<T>::C (&m)[9][TY + 2 * R][TX + 2 * R])
 {
     using C = typename Storage<T>::C;
     const StoreBases<T> sb = store_bases(dst, g, Y0);
@@ -555,7 +566,7 @@ __device__ __forceinline__ void lds_to_hbm(T* __restrict__ dst, const Geom& g, c
         const int x = X0 + tx, y = Y0 + ty;
         if (!INNER && (x >= g.nx || y >= g.ny)) continue;
         C d[9];
-        pull_lds<T, BC, TX + 2, TY + 2, INNER>(m, g, k.lid, tx + 1, ty + 1, x, y, d);
+        pull_lds<T, BC, TX + 2 * R, TY + 2 * R, INNER>(m, g, k.lid, tx + R, ty + R, x, y, d);
         collide<SCHEME, T>(d, k);
         scatter_store<T>(sb, g, x, y, d);
     }
@@ -581,15 +592,15 @@ __device__ __forceinline__ void workgroup_tile(const Geom& g, int TX, int TY, in
 // sum_r (TX + 2r)(TY + 2r) / (TX TY) - (S - 1) redundant collisions.  Same
 // per-node arithmetic, so the results are bitwise those of S one-step
 // launches.  A periodic lattice needs nx >= TX + 2(S - 1), ny >= TY + 2(S - 1).
+//
+// All steps share one LDS frame of the tile plus R = S - 1 rings, 9 planes of
+// FY x FX; the step held on the tile plus r rings occupies the frame's
+// window from (R - r, R - r), so a node has one frame position for every
+// step: it writes its new values where it pulled its own rest population.
 template <typename T, int TX, int TY, int S> struct MultiTile {
     using C = typename Storage<T>::C;
-    static constexpr int R = S - 1;
-    C buf[9 * (TX + 2 * R) * (TY + 2 * R)];
-    // the LDS viewed as the step held on the tile plus a ring of r nodes
-    template <int r> __device__ C (&ring())[9][TY + 2 * r][TX + 2 * r]
-    {
-        return *reinterpret_cast<C(*)[9][TY + 2 * r][TX + 2 * r]>(buf);
-    }
+    static constexpr int R = S - 1, FX = TX + 2 * R, FY = TY + 2 * R;
+    C m[9][FY][FX];
 };
 
 // A middle step: pull from the ring-(r+1) step in LDS, collide on the tile
@@ -599,7 +610,8 @@ __device__ __forceinline__ void middle_step(const Geom& g, const Coef<typename S
                                             MultiTile<T, TX, TY, S>& sh)
 {
     using C = typename Storage<T>::C;
-    constexpr int BX = TX + 2 * r, BY = TY + 2 * r, AX = BX + 2, AY = BY + 2;
+    using Tile = MultiTile<T, TX, TY, S>;
+    constexpr int BX = TX + 2 * r, BY = TY + 2 * r, OFF = Tile::R - r, FX = Tile::FX, FY = Tile::FY;
     constexpr int P = (BX * BY + NT - 1) / NT;
     C d[P][9];
     bool live[P];
@@ -615,22 +627,33 @@ __device__ __forceinline__ void middle_step(const Geom& g, const Coef<typename S
         else
             live[j] = i < BX * BY && (unsigned)x < (unsigned)g.nx && (unsigned)y < (unsigned)g.ny;
         if (live[j]) {
-            pull_lds<T, BC, AX, AY, INNER>(sh.template ring<r + 1>(), g, k.lid, lx + 1, ly + 1, x, y, d[j]);
+            pull_lds<T, BC, FX, FY, INNER>(sh.m, g, k.lid, lx + OFF, ly + OFF, x, y, d[j]);
             collide<SCHEME, T>(d[j], k);
             if constexpr (Storage<T>::kRounds) d[j][0] = Storage<T>::stored_value(d[j][0], 0);
         }
     }
     __syncthreads(); // every pull from the wider ring is done before it is overwritten
-    auto& m = sh.template ring<r>();
 #pragma unroll
     for (int j = 0; j < P; ++j) {
         if (!live[j]) continue;
         const int i = threadIdx.x + j * NT;
         const int lx = i % BX, ly = i / BX;
+        C* own = &sh.m[0][ly + OFF][lx + OFF];
 #pragma unroll
-        for (int a = 0; a < 9; ++a) m[a][ly][lx] = d[j][a];
+        for (int a = 0; a < 9; ++a) own[a * FX * FY] = d[j][a];
     }
     __syncthreads();
+}
+
+// Steps t+2 .. t+S of a tile whose step t+1 is in LDS.
+template <typename T, int SCHEME, int BC, int TX, int TY, int NT, int S, bool INNER>
+__device__ __forceinline__ void later_steps(T* __restrict__ dst, const Geom& g, const Coef<typename Storage<T>::C>& k,
+                                            int X0, int Y0, MultiTile<T, TX, TY, S>& sh)
+{
+    constexpr int R = S - 1;
+    if constexpr (R >= 3) middle_step<T, SCHEME, BC, TX, TY, NT, S, 2, INNER>(g, k, X0, Y0, sh);
+    if constexpr (R >= 2) middle_step<T, SCHEME, BC, TX, TY, NT, S, 1, INNER>(g, k, X0, Y0, sh);
+    lds_to_hbm<T, SCHEME, BC, TX, TY, NT, R, INNER>(dst, g, k, X0, Y0, sh.m);
 }
 
 template <typename T, int SCHEME, int BC, int TX, int TY, int NT, int S, bool INNER>
@@ -642,25 +665,28 @@ __device__ __forceinline__ void multi_tile_body(const T* __restrict__ src, T* __
     {
         RingRegs<T, TX + 2 * R, TY + 2 * R, NT> r;
         ring_load<T, BC, TX + 2 * R, TY + 2 * R, NT, R, INNER>(src, g, k.lid, X0, Y0, r);
-        ring_collide<T, SCHEME, TX + 2 * R, TY + 2 * R, NT>(k, r, sh.template ring<R>());
+        ring_collide<T, SCHEME, TX + 2 * R, TY + 2 * R, NT>(k, r, sh.m);
     }
     __syncthreads();
-    if constexpr (R >= 3) middle_step<T, SCHEME, BC, TX, TY, NT, S, 2, INNER>(g, k, X0, Y0, sh);
-    if constexpr (R >= 2) middle_step<T, SCHEME, BC, TX, TY, NT, S, 1, INNER>(g, k, X0, Y0, sh);
-    lds_to_hbm<T, SCHEME, BC, TX, TY, NT, INNER>(dst, g, k, X0, Y0, sh.template ring<1>());
+    later_steps<T, SCHEME, BC, TX, TY, NT, S, INNER>(dst, g, k, X0, Y0, sh);
 }
 
 // A tile whose widest region (the tile plus S - 1 rings) lies inside the
 // lattice, off its outer ring, needs no wrap, bounce-back or bounds checks:
 // most tiles of a large lattice take that copy of the code (same
 // arithmetic, so the same results).
+__device__ __forceinline__ bool inner_tile(const Geom& g, int X0, int Y0, int TX, int TY, int R)
+{
+    return X0 - R >= 1 && X0 + TX + R <= g.nx - 1 && Y0 - R >= 1 && Y0 + TY + R <= g.ny - 1;
+}
+
 template <typename T, int SCHEME, int BC, int TX, int TY, int NT, int S>
 __device__ __forceinline__ void multi_tile(const T* __restrict__ src, T* __restrict__ dst, const Geom& g,
                                            const Coef<typename Storage<T>::C>& k, int X0, int Y0,
                                            MultiTile<T, TX, TY, S>& sh)
 {
     constexpr int R = S - 1;
-    const bool inner = X0 - R >= 1 && X0 + TX + R <= g.nx - 1 && Y0 - R >= 1 && Y0 + TY + R <= g.ny - 1;
+    const bool inner = inner_tile(g, X0, Y0, TX, TY, R);
     if (inner)
         multi_tile_body<T, SCHEME, BC, TX, TY, NT, S, true>(src, dst, g, k, X0, Y0, sh);
     else
