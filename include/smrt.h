@@ -101,8 +101,11 @@ size_t smrt_workspace_bytes(const smrt_params* p);
  * dev_ws: caller-owned device memory of at least smrt_workspace_bytes(p)
  * bytes, 256-byte aligned, kept alive until smrt_destroy; or NULL to let the
  * library allocate (and later free) it.  ws_bytes is ignored when dev_ws is
- * NULL.  SMRT_EINVAL: nx or ny < 3, unknown enum, relaxation time <= 1/2,
- * |u_lid| >= 1/sqrt(3), non-zero reserved fields, out == NULL.  SMRT_ENOMEM:
+ * NULL.  SMRT_EINVAL: nx or ny < 3, nx * ny > 2^34, a row of more than
+ * 2 MiB of stored values (nx > 262,144 for SMRT_F64, 524,288 for SMRT_F32,
+ * 1,048,576 for 16-bit storage: the kernels address a tile through 32-bit
+ * byte offsets), unknown enum, relaxation time <= 1/2, |u_lid| >= 1/sqrt(3),
+ * non-zero reserved fields, out == NULL.  SMRT_ENOMEM:
  * ws_bytes too small or the allocation failed.  On error *out is NULL. */
 int smrt_create(const smrt_params* p, void* dev_ws, size_t ws_bytes, smrt_ctx** out);
 
@@ -247,7 +250,8 @@ size_t smrt_batch_workspace_bytes(const smrt_batch_params* p);
  * capture stream (default priority).  Default launch: 64 x 16 tiles with
  * four time steps per launch (FP32 storage) or three (16-bit storage); FP64
  * storage one step with 64 x 4 blocks; one workgroup per tile.  Errors as for
- * smrt_create. */
+ * smrt_create, per cavity; also SMRT_EINVAL when the tile table would exceed
+ * 2^31 - 1 entries. */
 int smrt_batch_create(const smrt_batch_params* p, void* dev_ws, size_t ws_bytes, smrt_batch** out);
 
 /* Enqueues n time steps of every running cavity (asynchronous). */

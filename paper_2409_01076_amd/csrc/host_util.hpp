@@ -9,6 +9,12 @@
 
 namespace smrt_host {
 
+// Largest lattice row, in bytes of stored values.  Inside a tile the kernels
+// address HBM through 32-bit byte offsets from the tile's first row (a
+// one-step tile spans at most 512 rows plus its halo), so 2 MiB rows keep
+// every offset below 2^31.
+constexpr long long kMaxRowBytes = 1LL << 21;
+
 extern thread_local std::string g_error;
 
 // Records a printf-style message and returns `code`.

@@ -163,6 +163,9 @@ int check_params(const smrt_params* p, double* tau_out)
     if (p->boundary != SMRT_CAVITY && p->boundary != SMRT_PERIODIC)
         return fail(SMRT_EINVAL, "unknown boundary %d", p->boundary);
     if (elem_bytes(p->storage) == 0) return fail(SMRT_EINVAL, "unknown storage type %d", p->storage);
+    if ((long long)p->nx * (long long)elem_bytes(p->storage) > smrt_host::kMaxRowBytes)
+        return fail(SMRT_EINVAL, "rows of %d nodes exceed %lld bytes of stored values", p->nx,
+                    smrt_host::kMaxRowBytes);
     if (p->reserved0 != 0) return fail(SMRT_EINVAL, "reserved0 must be 0");
     for (int i = 0; i < 4; ++i)
         if (p->reserved[i] != 0) return fail(SMRT_EINVAL, "reserved[%d] must be 0", i);

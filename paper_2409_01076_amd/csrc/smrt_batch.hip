@@ -43,9 +43,9 @@ constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 // Steps per captured graph (even, so a replay leaves the buffer parity as it was).
 constexpr int kGraphSteps = 64;
 
-int tiles_of(int nx, int ny, smrt::BatchLaunch L)
+int64_t tiles_of(int nx, int ny, smrt::BatchLaunch L)
 {
-    return ((nx + L.bx - 1) / L.bx) * ((ny + L.by - 1) / L.by);
+    return (int64_t)((nx + L.bx - 1) / L.bx) * ((ny + L.by - 1) / L.by);
 }
 
 struct Plan {
@@ -79,10 +79,15 @@ int make_plan(const smrt_batch_params* p, Plan* out)
     P.desc.resize(p->count);
     P.tau.resize(p->count);
     size_t elems = 0, snap = 0;
-    std::vector<int> tiles_per_shape(kNumShapes, 0);
+    std::vector<int64_t> tiles_per_shape(kNumShapes, 0);
     for (int i = 0; i < p->count; ++i) {
         const int nx = p->nx[i], ny = p->ny[i];
         if (nx < 3 || ny < 3) return fail(SMRT_EINVAL, "cavity %d: nx and ny must be >= 3 (got %d x %d)", i, nx, ny);
+        if ((int64_t)nx * ny > (int64_t)1 << 34)
+            return fail(SMRT_EINVAL, "cavity %d: %d x %d nodes is too large", i, nx, ny);
+        if ((long long)nx * (long long)e > smrt_host::kMaxRowBytes)
+            return fail(SMRT_EINVAL, "cavity %d: rows of %d nodes exceed %lld bytes of stored values", i, nx,
+                        smrt_host::kMaxRowBytes);
         double tau = p->tau ? p->tau[i] : 0.0;
         if (!(tau > 0.0)) {
             const double re = p->re ? p->re[i] : 0.0;
@@ -115,7 +120,10 @@ int make_plan(const smrt_batch_params* p, Plan* out)
         P.tau[i] = tau;
         for (int s = 0; s < kNumShapes; ++s) tiles_per_shape[s] += tiles_of(nx, ny, kShapes[s]);
     }
-    P.max_tiles = *std::max_element(tiles_per_shape.begin(), tiles_per_shape.end());
+    const int64_t max_tiles = *std::max_element(tiles_per_shape.begin(), tiles_per_shape.end());
+    if (max_tiles > std::numeric_limits<int>::max())
+        return fail(SMRT_EINVAL, "batch of %lld tiles is too large", (long long)max_tiles);
+    P.max_tiles = (int)max_tiles;
     P.state_elems = elems;
     P.snap_doubles = snap;
     // partial rows: one per tile in the batch reduction, and up to 2048 blocks
@@ -198,7 +206,7 @@ int upload_tables(smrt_batch* b)
     b->table_order.clear();
     for (int i = 0; i < b->p.count; ++i) {
         if (b->status[i] != SMRT_RUNNING) continue;
-        const int n = tiles_of(desc[i].nx, desc[i].ny, b->shape);
+        const int n = (int)tiles_of(desc[i].nx, desc[i].ny, b->shape); // the plan keeps the sum in int range
         ranges.push_back(make_int2((int)table.size(), n));
         for (int t = 0; t < n; ++t) table.push_back(make_int2(i, t));
         b->table_order.push_back(i);
@@ -473,9 +481,9 @@ int smrt_batch_create(const smrt_batch_params* p, void* dev_ws, size_t ws_bytes,
         // steps per launch (FP32) or three (16-bit), as for single lattices.
         b->shape = p->storage == SMRT_F64 ? kShapes[0] : smrt::BatchLaunch{64, 16};
         b->multi = p->storage == SMRT_F64 ? 1 : p->storage == SMRT_F32 ? 4 : 3;
-        int total_tiles = 0;
+        int64_t total_tiles = 0;
         for (const auto& c : b->plan.desc) total_tiles += tiles_of(c.nx, c.ny, b->shape);
-        b->grid = total_tiles;
+        b->grid = (int)total_tiles; // at most the plan's max_tiles
         rc = upload_tables(b);
         if (rc) {
             smrt_batch_destroy(b);

@@ -75,6 +75,44 @@ def test_workspace_bytes_host_only():
     assert smrt.workspace_bytes(nx=4096, ny=4096, storage="f32", tau=0.4) == 0
 
 
+@pytest.mark.parametrize("storage,widest", [("f64", 262_144), ("f32", 524_288), ("f16", 1_048_576),
+                                             ("bf16", 1_048_576)])
+def test_row_width_limit(storage, widest):
+    # a lattice row holds at most 2 MiB of stored values (32-bit offsets inside a tile)
+    from paper_2409_01076_amd import smrt
+    assert smrt.workspace_bytes(nx=widest, ny=3, storage=storage, tau=0.6) > 0
+    assert smrt.workspace_bytes(nx=widest + 1, ny=3, storage=storage, tau=0.6) == 0
+    rc, ctx, msg = _create(nx=widest + 1, ny=3, storage=storage, tau=0.6)
+    assert rc == smrt.EINVAL and ctx is None and "bytes of stored values" in msg
+    # nodes are capped at 2^34 whatever the width
+    assert smrt.workspace_bytes(nx=4096, ny=(1 << 22) + 1, storage=storage, tau=0.6) == 0
+
+
+def _batch_bytes(nx, ny, storage="f32"):
+    from paper_2409_01076_amd import smrt
+    c = len(nx)
+    p = smrt.BatchParams()
+    p.count, p.scheme, p.storage = c, smrt.SCHEMES["smrt"], smrt.STORAGE[storage]
+    anx, any_ = (ctypes.c_int32 * c)(*nx), (ctypes.c_int32 * c)(*ny)
+    tau = (ctypes.c_double * c)(*([0.6] * c))
+    p.nx = ctypes.cast(anx, ctypes.POINTER(ctypes.c_int32))
+    p.ny = ctypes.cast(any_, ctypes.POINTER(ctypes.c_int32))
+    p.tau = ctypes.cast(tau, ctypes.POINTER(ctypes.c_double))
+    p.u_lid = 0.1
+    lib = smrt.load()
+    n = lib.smrt_batch_workspace_bytes(ctypes.byref(p))
+    return n, lib.smrt_last_error().decode()
+
+
+def test_batch_row_width_and_size_limits():
+    n, _ = _batch_bytes([64, 524_288], [64, 3])
+    assert n > 0
+    n, msg = _batch_bytes([64, 524_289], [64, 3])
+    assert n == 0 and "cavity 1" in msg and "bytes of stored values" in msg
+    n, msg = _batch_bytes([4096], [(1 << 22) + 1])
+    assert n == 0 and "too large" in msg
+
+
 def test_null_context_calls_fail_cleanly():
     from paper_2409_01076_amd import smrt
     lib = smrt.load()
