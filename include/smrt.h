@@ -167,17 +167,18 @@ int smrt_set_launch(smrt_ctx* c, int32_t bx, int32_t by, int32_t rows);
  * 1/S.  Tiles (tile_cols x tile_rows): two steps {64 x 4, 64 x 8, 64 x 16,
  * 64 x 32, 128 x 4, 128 x 8} (0 = 64 x 8); three and four steps {64 x 8,
  * 64 x 16, 64 x 24, 64 x 26} (0 = 64 x 16); FP64 storage (twice the LDS per
- * node) two steps {64 x 4, 64 x 8}, three and four steps {64 x 8} (0 = 64 x
- * 8).  Tiles of 1024 nodes or more run 512 threads per workgroup, smaller
- * ones 256.  A periodic lattice needs nx >= tile_cols + 2r and ny >=
- * tile_rows + 2r with r = steps - 1.  Per node the arithmetic is unchanged:
- * results are bitwise those of single-step launches.  Default at creation:
- * FP32 storage 4 steps with a 64 x 26 tile while that gives >= 1024 tiles,
- * else with 64 x 16 while that gives >= 256; 16-bit storage 3 steps with
- * 64 x 16 while that gives >= 1024; smaller lattices 2 steps with a 64 x 32
- * tile while that gives >= 512 tiles, else with 64 x 4; FP64 storage 4
- * steps with 64 x 8 tiles; lattices too small for the rings: 1.  A step count that is not a multiple
- * ends with one shorter launch.  With steps = 1 the tile arguments are
+ * node) two steps {64 x 4, 64 x 8}, three steps {64 x 8}, four steps
+ * {64 x 8, 64 x 10} (0 = 64 x 8).  Four-step tiles of 512 nodes or more and
+ * two-step 64 x 32 tiles run 768 threads per workgroup, other tiles of 1024
+ * nodes or more 512, the rest 256.  A periodic lattice needs nx >=
+ * tile_cols + 2r and ny >= tile_rows + 2r with r = steps - 1.  Per node the
+ * arithmetic is unchanged: results are bitwise those of single-step
+ * launches.  Default at creation: FP32 and 16-bit storage 4 steps with a
+ * 64 x 26 tile while that gives >= 1024 tiles, else with 64 x 16 while that
+ * gives >= 256; smaller lattices 2 steps with a 64 x 32 tile while that
+ * gives >= 512 tiles, else with 64 x 4; FP64 storage 4 steps with 64 x 10
+ * tiles; lattices too small for the rings: 1.  A step count that is not a
+ * multiple ends with one shorter launch.  With steps = 1 the tile arguments are
  * ignored.  SMRT_EINVAL if not applicable. */
 int smrt_set_steps_per_launch(smrt_ctx* c, int32_t steps, int32_t tile_cols, int32_t tile_rows);
 

@@ -268,14 +268,21 @@ template <typename T> int launch_step(smrt_ctx* c, const void* src, void* dst)
     return SMRT_OK;
 }
 
-// Threads per multi-step workgroup: 512 for tiles of 1024 nodes or more.
-constexpr int multi_threads(int tx, int ty) { return tx * ty >= 1024 ? 512 : 256; }
+// Threads per multi-step workgroup.  Four-step tiles of 512 nodes or more
+// and two-step 64 x 32 tiles take 768: with two workgroups per CU (LDS-bound)
+// that is 6 waves per SIMD, which hides more of the latency between the
+// HBM and LDS phases (1024 measured slower); other tiles of 1024 nodes or
+// more take 512, the rest 256.
+constexpr int multi_threads(int steps, int tx, int ty)
+{
+    return (steps == 4 && tx * ty >= 512) || (steps == 2 && tx * ty >= 2048) ? 768 : tx * ty >= 1024 ? 512 : 256;
+}
 
 template <typename T, int SCHEME, int BC, int TX, int TY, int STEPS>
 int launch_multi(smrt_ctx* c, const T* s, T* d, const smrt::Geom& g,
                  const smrt::Coef<typename smrt::Storage<T>::C>& k, int ntiles)
 {
-    constexpr int NT = multi_threads(TX, TY);
+    constexpr int NT = multi_threads(STEPS, TX, TY);
     if constexpr (STEPS == 4)
         smrt::stream_collide_x4<T, SCHEME, BC, TX, TY, NT><<<ntiles, NT, 0, c->stream>>>(s, d, g, k);
     else if constexpr (STEPS == 3)
@@ -362,7 +369,8 @@ template <typename T> int launch_k(smrt_ctx* c, int k, int cols, int rows, const
 // two steps and 64 x 8 for three and four.
 int launch_k_f64(smrt_ctx* c, int k, int rows, const void* src, void* dst)
 {
-    if (k == 4) return launch_multi_tile<double, 4, 64, 8>(c, src, dst);
+    if (k == 4) return rows == 10 ? launch_multi_tile<double, 4, 64, 10>(c, src, dst)
+                                  : launch_multi_tile<double, 4, 64, 8>(c, src, dst);
     if (k == 3) return launch_multi_tile<double, 3, 64, 8>(c, src, dst);
     if (rows == 4) return launch_multi_tile<double, 2, 64, 4>(c, src, dst);
     return launch_multi_tile<double, 2, 64, 8>(c, src, dst);
@@ -483,21 +491,21 @@ int smrt_create(const smrt_params* p, void* dev_ws, size_t ws_bytes, smrt_ctx** 
         // lattice allows (512 measured best on 4096^2, within 1-2% of 256).
         // FP32 and 16-bit storage take the LDS-blocked kernels, tiles in XCD
         // panels of 16 tile columns, 512 threads per workgroup.  Measured on
-        // 512^2 .. 4096^2: FP32 four steps per launch, with 64 x 26 tiles
-        // while that gives >= 1024 workgroups (the tall tile leaves fewer
-        // idle lanes on the rings), else 64 x 16 while that gives >= 256;
-        // 16-bit storage three steps with 64 x 16 tiles while that gives >=
-        // 1024; smaller lattices two steps with 64 x 32 tiles while that
-        // gives >= 512 workgroups, else with 64 x 4.  Periodic lattices need
-        // room for the rings.
+        // 512^2 .. 4096^2: FP32 and 16-bit storage four steps per launch,
+        // with 64 x 26 tiles while that gives >= 1024 workgroups (the tall
+        // tile leaves fewer idle lanes on the rings), else 64 x 16 while that
+        // gives >= 256; smaller lattices two steps with 64 x 32 tiles while
+        // that gives >= 512 workgroups, else with 64 x 4.  Periodic lattices
+        // need room for the rings.
         if (p->storage == SMRT_F64) {
-            // FP64 (twice the LDS per node): four steps with 64 x 8 tiles,
-            // measured best on 512^2 .. 4096^2 (2.5x one step on 4096^2), in
-            // XCD panels of 32 tile columns (17 % faster than 8 on 4096^2).
+            // FP64 (twice the LDS per node): four steps with 64 x 10 tiles
+            // (80.6 KB of LDS, two workgroups per CU), measured best on
+            // 512^2 .. 4096^2 (3x one step on 4096^2), in XCD panels of 32
+            // tile columns (17 % faster than 8 on 4096^2).
             c->fused_cols = 64;
-            c->fused_rows = 8;
+            c->fused_rows = 10;
             c->panel = 32;
-            if (p->boundary == SMRT_CAVITY || (p->nx >= 70 && p->ny >= 14)) c->fused = 4;
+            if (p->boundary == SMRT_CAVITY || (p->nx >= 70 && p->ny >= 16)) c->fused = 4;
         } else {
             const int64_t cols = (p->nx + 63) / 64;
             const auto tiles = [&](int rows) { return cols * ((p->ny + rows - 1) / rows); };
@@ -507,14 +515,11 @@ int smrt_create(const smrt_params* p, void* dev_ws, size_t ws_bytes, smrt_ctx** 
             };
             c->fused_cols = 64;
             c->panel = 16;
-            if (p->storage == SMRT_F32 && tiles(26) >= 1024 && fits(4, 26)) {
+            if (tiles(26) >= 1024 && fits(4, 26)) {
                 c->fused = 4;
                 c->fused_rows = 26;
-            } else if (p->storage == SMRT_F32 && tiles(16) >= 256 && fits(4, 16)) {
+            } else if (tiles(16) >= 256 && fits(4, 16)) {
                 c->fused = 4;
-                c->fused_rows = 16;
-            } else if (p->storage != SMRT_F32 && tiles(16) >= 1024 && fits(3, 16)) {
-                c->fused = 3;
                 c->fused_rows = 16;
             } else {
                 c->fused_rows = tiles(32) >= 512 ? 32 : 4;
@@ -718,7 +723,7 @@ int smrt_set_steps_per_launch(smrt_ctx* c, int32_t steps, int32_t tile_cols, int
     if (tile_rows == 0) tile_rows = steps >= 3 && c->p.storage != SMRT_F64 ? 16 : 8;
     bool ok;
     if (c->p.storage == SMRT_F64)
-        ok = tile_cols == 64 && (tile_rows == 8 || (steps == 2 && tile_rows == 4));
+        ok = tile_cols == 64 && (tile_rows == 8 || (steps == 4 && tile_rows == 10) || (steps == 2 && tile_rows == 4));
     else
         ok = steps >= 3 ? tile_cols == 64 && (tile_rows == 8 || tile_rows == 16 || tile_rows == 24 || tile_rows == 26)
                         : (tile_cols == 64 && (tile_rows == 4 || tile_rows == 8 || tile_rows == 16 || tile_rows == 32)) ||

@@ -226,13 +226,15 @@ int upload_tables(smrt_batch* b)
     return SMRT_OK;
 }
 
-// Threads per multi-step workgroup: 512 for 64 x 16 tiles, 256 for smaller.
-constexpr int multi_threads(int ty) { return ty >= 16 ? 512 : 256; }
+// Threads per multi-step workgroup, as for single lattices: 768 for
+// four-step tiles (64 x 8 and 64 x 16), 512 for other 64 x 16 tiles, 256 for
+// smaller.
+constexpr int multi_threads(int steps, int ty) { return steps == 4 && ty >= 8 ? 768 : ty >= 16 ? 512 : 256; }
 
 template <typename T, int SCHEME, int TY>
 void launch_two_tile(smrt_batch* b, hipStream_t s, int parity, dim3 grid)
 {
-    constexpr int NT = multi_threads(TY);
+    constexpr int NT = multi_threads(2, TY);
     smrt::batch_stream_collide_x2<T, SCHEME, 64, TY, NT><<<grid, NT, 0, s>>>(
         b->desc(), b->table(), b->ntiles_dev(), reinterpret_cast<T*>(b->state()), parity);
 }
@@ -240,7 +242,7 @@ void launch_two_tile(smrt_batch* b, hipStream_t s, int parity, dim3 grid)
 template <typename T, int SCHEME, int TY>
 void launch_three_tile(smrt_batch* b, hipStream_t s, int parity, dim3 grid)
 {
-    constexpr int NT = multi_threads(TY);
+    constexpr int NT = multi_threads(3, TY);
     smrt::batch_stream_collide_x3<T, SCHEME, 64, TY, NT><<<grid, NT, 0, s>>>(
         b->desc(), b->table(), b->ntiles_dev(), reinterpret_cast<T*>(b->state()), parity);
 }
@@ -248,7 +250,7 @@ void launch_three_tile(smrt_batch* b, hipStream_t s, int parity, dim3 grid)
 template <typename T, int SCHEME, int TY>
 void launch_four_tile(smrt_batch* b, hipStream_t s, int parity, dim3 grid)
 {
-    constexpr int NT = multi_threads(TY);
+    constexpr int NT = multi_threads(4, TY);
     smrt::batch_stream_collide_x4<T, SCHEME, 64, TY, NT><<<grid, NT, 0, s>>>(
         b->desc(), b->table(), b->ntiles_dev(), reinterpret_cast<T*>(b->state()), parity);
 }
@@ -592,7 +594,7 @@ int smrt_batch_autotune(smrt_batch* b, int32_t steps, int32_t* chosen)
         b->multi = multi;
         rc = upload_tables(b);
         if (rc) break;
-        const int per_block_waves = multi > 1 ? multi_threads(b->shape.by) / 64 : (b->shape.bx * b->shape.by) / 64;
+        const int per_block_waves = multi > 1 ? multi_threads(multi, b->shape.by) / 64 : (b->shape.bx * b->shape.by) / 64;
         const int grids[] = {b->ntiles, cus * std::max(1, 8 / per_block_waves), cus * std::max(1, 16 / per_block_waves),
                              cus * std::max(1, 32 / per_block_waves)};
         for (int gi = 0; gi < 4; ++gi) {

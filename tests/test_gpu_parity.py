@@ -405,9 +405,9 @@ def test_tile_order_does_not_change_results(smrt, boundary, tile):
 
 @pytest.mark.parametrize("boundary", ["periodic", "cavity"])
 @pytest.mark.parametrize("scheme", ["srt", "smrt", "trt"])
-@pytest.mark.parametrize("multi,tile", [(2, (64, 4)), (2, (64, 8)), (3, (64, 8)), (4, (64, 8))])
+@pytest.mark.parametrize("multi,tile", [(2, (64, 4)), (2, (64, 8)), (3, (64, 8)), (4, (64, 8)), (4, (64, 10))])
 def test_multi_step_kernel_fp64_equals_single_steps(smrt, boundary, scheme, multi, tile):
-    """FP64 storage (64 x 4 and 64 x 8 tiles): bitwise equal to one-step launches."""
+    """FP64 storage (64 x 4, 64 x 8 and 64 x 10 tiles): bitwise equal to one-step launches."""
     nx, ny = 203, 77
     f0 = inputs.perturbed_populations(nx, ny, eps=0.03, seed=9)
     u = 0.1 if boundary == "cavity" else 0.0
@@ -496,14 +496,16 @@ def test_three_step_kernel_rejects_unsupported(smrt):
         s.set_steps_per_launch(4)                      # 70 >= 64 + 6, 100 >= 16 + 6
 
 
-@pytest.mark.parametrize("n,boundary,steps", [(4096, "periodic", 402), (1024, "cavity", 4001)])
-def test_default_launch_long_run_bitwise(smrt, n, boundary, steps):
-    """The default launch configuration (four steps per launch, 64 x 26 tiles on
-    4096^2, 64 x 16 on 1024^2) over many launches at the benchmark sizes:
-    populations bitwise those of one step per launch, compared on the device."""
+@pytest.mark.parametrize("n,boundary,steps,storage", [(4096, "periodic", 402, "f32"), (1024, "cavity", 4001, "f32"),
+                                                     (1024, "cavity", 1001, "f64"), (2048, "periodic", 402, "f16")])
+def test_default_launch_long_run_bitwise(smrt, n, boundary, steps, storage):
+    """The default launch configuration (four steps per launch: 64 x 26 tiles on
+    4096^2 and 2048^2, 64 x 16 on 1024^2, 64 x 10 for FP64 storage) over many
+    launches at the benchmark sizes: populations bitwise those of one step per
+    launch, compared on the device."""
     outs = []
     for default in (True, False):
-        with smrt.Solver(n, n, scheme="smrt", boundary=boundary, storage="f32", tau=0.6,
+        with smrt.Solver(n, n, scheme="smrt", boundary=boundary, storage=storage, tau=0.6,
                          u_lid=0.1 if boundary == "cavity" else 0.0) as s:
             if boundary == "periodic":
                 s.init_fields(*(to_dev(a) for a in inputs.taylor_green(n, n)))
@@ -540,5 +542,8 @@ def test_two_step_kernel_rejects_unsupported(smrt):
         with pytest.raises(smrt.SmrtError):
             s.set_steps_per_launch(2, tile_rows=16)   # FP64: tile not offered
         s.set_steps_per_launch(4)                      # FP64: 64 x 8 tiles
+        s.set_steps_per_launch(4, tile_rows=10)        # FP64: 64 x 10, four steps only
+        with pytest.raises(smrt.SmrtError):
+            s.set_steps_per_launch(3, tile_rows=10)
         with pytest.raises(smrt.SmrtError):
             s.set_steps_per_launch(5)
