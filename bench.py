@@ -521,7 +521,7 @@ def main():
     s = STORAGE_BYTES[args.storage]
     # The dominant kernel reads d(t) and writes d(t + spl) once per node per
     # launch: 9 loads + 9 stores per node whether it advances one time step
-    # (stream_collide) or several through LDS (stream_collide_x2 .. _x4).
+    # (stream_collide) or several through LDS (stream_collide_x2 .. _x5).
     kernel_name = "stream_collide" if spl == 1 else "stream_collide_x%d" % spl
     launch_ms = (window_ms - rem_ms) / q
     alg_bytes = 18 * s * cells

@@ -160,29 +160,32 @@ double smrt_tau(const smrt_ctx* c);
  * SMRT_EINVAL otherwise. */
 int smrt_set_launch(smrt_ctx* c, int32_t bx, int32_t by, int32_t rows);
 
-/* Time steps per kernel launch: 1 .. 4.  The multi-step kernels keep the
- * intermediate steps on chip: with S steps, step t+1 is held in LDS on the
- * tile plus a ring of S - 1 nodes, each later step on a ring one node
- * narrower, written over the same LDS.  HBM traffic per node-update falls to
- * 1/S.  Tiles (tile_cols x tile_rows): two steps {64 x 4, 64 x 8, 64 x 16,
- * 64 x 32, 128 x 4, 128 x 8} (0 = 64 x 8); three and four steps {64 x 8,
- * 64 x 16, 64 x 24, 64 x 26} (0 = 64 x 16); FP64 storage (twice the LDS per
- * node) two steps {64 x 4, 64 x 8}, three steps {64 x 8}, four steps
- * {64 x 8, 64 x 10} (0 = 64 x 8).  Four-step tiles of 512 nodes or more and
- * two-step 64 x 32 tiles run 768 threads per workgroup, other tiles of 1024
- * nodes or more 512, the rest 256.  A periodic lattice needs nx >=
- * tile_cols + 2r and ny >= tile_rows + 2r with r = steps - 1.  Per node the
- * arithmetic is unchanged: results are bitwise those of single-step
- * launches.  Default at creation: FP32 and 16-bit storage 4 steps with a
- * 64 x 26 tile while that gives >= 1024 tiles, else with 64 x 16 while that
- * gives >= 256; smaller lattices 2 steps with a 64 x 32 tile while that
- * gives >= 512 tiles, else with 64 x 4; FP64 storage 4 steps with 64 x 10
- * tiles; lattices too small for the rings: 1.  A step count that is not a
- * multiple ends with one shorter launch.  With steps = 1 the tile arguments are
- * ignored.  SMRT_EINVAL if not applicable. */
+/* Time steps per kernel launch: 1 .. 5 (FP64 storage 1 .. 4).  The
+ * multi-step kernels keep the intermediate steps on chip: with S steps, step
+ * t+1 is held in LDS on the tile plus a ring of S - 1 nodes, each later step
+ * on a ring one node narrower, written over the same LDS.  HBM traffic per
+ * node-update falls to 1/S.  Tiles (tile_cols x tile_rows): two steps {64 x
+ * 4, 64 x 8, 64 x 16, 64 x 32, 128 x 4, 128 x 8} (0 = 64 x 8); three and four
+ * steps {64 x 8, 64 x 16, 64 x 24, 64 x 26} (0 = 64 x 16); five steps
+ * {64 x 16, 64 x 22} (0 = 64 x 16); FP64 storage (twice the LDS per node) two
+ * steps {64 x 4, 64 x 8}, three steps {64 x 8}, four steps {64 x 8, 64 x 10}
+ * (0 = 64 x 8).  Four- and five-step tiles of 512 nodes or more and two-step
+ * 64 x 32 tiles run 768 threads per workgroup, other tiles of 1024 nodes or
+ * more 512, the rest 256.  A periodic lattice needs nx >= tile_cols + 2r and
+ * ny >= tile_rows + 2r with r = steps - 1.  Per node the arithmetic is
+ * unchanged: results are bitwise those of single-step launches.  Default at
+ * creation: FP32 storage 5 steps with a 64 x 22 tile while that gives >= 1024
+ * tiles, else with 64 x 16 while that gives >= 256; 16-bit storage 4 steps
+ * with a 64 x 26 tile while that gives >= 1024 tiles, else with 64 x 16
+ * while that gives >= 256; smaller lattices 2 steps with a 64 x 32 tile
+ * while that gives >= 512 tiles, else with 64 x 4; FP64 storage 4 steps with
+ * 64 x 10 tiles; lattices too small for the rings: 1.  A step count that is
+ * not a multiple ends with one shorter launch (64 x 16 tiles, or 64 x 8 after
+ * a mode with shorter tiles).  With steps = 1 the tile arguments are ignored.
+ * SMRT_EINVAL if not applicable. */
 int smrt_set_steps_per_launch(smrt_ctx* c, int32_t steps, int32_t tile_cols, int32_t tile_rows);
 
-/* Time steps per launch in use (1 .. 4); -1 for c == NULL. */
+/* Time steps per launch in use (1 .. 5); -1 for c == NULL. */
 int32_t smrt_get_steps_per_launch(const smrt_ctx* c);
 
 /* Order in which the two-step kernel's workgroups take their tiles (a

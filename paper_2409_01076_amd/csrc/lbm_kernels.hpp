@@ -12,9 +12,9 @@
 // (Eq. feq-full) and the collision, and writes nine aligned values.  One step
 // per launch (stream_collide) is bound by HBM traffic: 9 loads and 9 stores
 // per node, about 70 vector instructions.  The multi-step kernels
-// (stream_collide_x2 .. _x4) keep the intermediate steps of a tile in LDS, so
-// HBM traffic per node-update falls to 1/S and the vector ALU becomes the
-// co-limit.
+// (stream_collide_x2 .. _x5) keep the intermediate steps of a tile in LDS, so
+// HBM traffic per node-update falls to 1/S; the latency between their HBM
+// and LDS phases and the vector ALU then bound them.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -583,7 +583,7 @@ __device__ __forceinline__ void workgroup_tile(const Geom& g, int TX, int TY, in
     Y0 = ty * TY;
 }
 
-// S time steps per launch (S = 2, 3, 4) on a TX x TY tile.  Step t+1 is
+// S time steps per launch (S = 2 .. 5) on a TX x TY tile.  Step t+1 is
 // computed on the tile plus a ring of S - 1 nodes (pulled from HBM) into LDS;
 // each further step t+s (s < S) is pulled from LDS on the tile plus a ring of
 // S - s nodes, collided into registers and, after a barrier, written over the
@@ -645,15 +645,24 @@ __device__ __forceinline__ void middle_step(const Geom& g, const Coef<typename S
     __syncthreads();
 }
 
+// The middle steps on rings r, r - 1, .., 1.
+template <typename T, int SCHEME, int BC, int TX, int TY, int NT, int S, int r, bool INNER>
+__device__ __forceinline__ void middle_steps(const Geom& g, const Coef<typename Storage<T>::C>& k, int X0, int Y0,
+                                             MultiTile<T, TX, TY, S>& sh)
+{
+    if constexpr (r >= 1) {
+        middle_step<T, SCHEME, BC, TX, TY, NT, S, r, INNER>(g, k, X0, Y0, sh);
+        middle_steps<T, SCHEME, BC, TX, TY, NT, S, r - 1, INNER>(g, k, X0, Y0, sh);
+    }
+}
+
 // Steps t+2 .. t+S of a tile whose step t+1 is in LDS.
 template <typename T, int SCHEME, int BC, int TX, int TY, int NT, int S, bool INNER>
 __device__ __forceinline__ void later_steps(T* __restrict__ dst, const Geom& g, const Coef<typename Storage<T>::C>& k,
                                             int X0, int Y0, MultiTile<T, TX, TY, S>& sh)
 {
-    constexpr int R = S - 1;
-    if constexpr (R >= 3) middle_step<T, SCHEME, BC, TX, TY, NT, S, 2, INNER>(g, k, X0, Y0, sh);
-    if constexpr (R >= 2) middle_step<T, SCHEME, BC, TX, TY, NT, S, 1, INNER>(g, k, X0, Y0, sh);
-    lds_to_hbm<T, SCHEME, BC, TX, TY, NT, R, INNER>(dst, g, k, X0, Y0, sh.m);
+    middle_steps<T, SCHEME, BC, TX, TY, NT, S, S - 2, INNER>(g, k, X0, Y0, sh);
+    lds_to_hbm<T, SCHEME, BC, TX, TY, NT, S - 1, INNER>(dst, g, k, X0, Y0, sh.m);
 }
 
 template <typename T, int SCHEME, int BC, int TX, int TY, int NT, int S, bool INNER>
@@ -721,6 +730,16 @@ __global__ void __launch_bounds__(NT) stream_collide_x4(const T* __restrict__ sr
     int X0, Y0;
     workgroup_tile(g, TX, TY, X0, Y0);
     multi_tile<T, SCHEME, BC, TX, TY, NT, 4>(src, dst, g, k, X0, Y0, sh);
+}
+
+template <typename T, int SCHEME, int BC, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT) stream_collide_x5(const T* __restrict__ src, T* __restrict__ dst, Geom g,
+                                                        Coef<typename Storage<T>::C> k)
+{
+    __shared__ MultiTile<T, TX, TY, 5> sh;
+    int X0, Y0;
+    workgroup_tile(g, TX, TY, X0, Y0);
+    multi_tile<T, SCHEME, BC, TX, TY, NT, 5>(src, dst, g, k, X0, Y0, sh);
 }
 
 // ---------------------------------------------------------------------------

@@ -201,7 +201,7 @@ struct smrt_ctx {
     int cur = 0;                   // 0: state in buffer A, 1: in buffer B
     int64_t steps = 0, snap_step = 0;
     int bx = 256, by = 1, rows = 1;
-    int fused = 1;                 // time steps per launch (1, or 2 .. 4 with the LDS-blocked kernels)
+    int fused = 1;                 // time steps per launch (1, or 2 .. 5 with the LDS-blocked kernels)
     int fused_cols = 64, fused_rows = 8; // tile of the multi-step kernels
     int panel = 0;                 // multi-step kernels: tile order (0 = row-major)
 
@@ -268,14 +268,15 @@ template <typename T> int launch_step(smrt_ctx* c, const void* src, void* dst)
     return SMRT_OK;
 }
 
-// Threads per multi-step workgroup.  Four-step tiles of 512 nodes or more
-// and two-step 64 x 32 tiles take 768: with two workgroups per CU (LDS-bound)
-// that is 6 waves per SIMD, which hides more of the latency between the
-// HBM and LDS phases (1024 measured slower); other tiles of 1024 nodes or
-// more take 512, the rest 256.
+// Threads per multi-step workgroup.  Four- and five-step tiles of 512 nodes
+// or more and two-step 64 x 32 tiles take 768: with two workgroups per CU
+// (LDS-bound) that is 6 waves per SIMD, which hides more of the latency
+// between the HBM and LDS phases (512 and 1024 measured slower, 640 and 896,
+// which load the four SIMDs unevenly, much slower); other tiles of 1024
+// nodes or more take 512, the rest 256.
 constexpr int multi_threads(int steps, int tx, int ty)
 {
-    return (steps == 4 && tx * ty >= 512) || (steps == 2 && tx * ty >= 2048) ? 768 : tx * ty >= 1024 ? 512 : 256;
+    return (steps >= 4 && tx * ty >= 512) || (steps == 2 && tx * ty >= 2048) ? 768 : tx * ty >= 1024 ? 512 : 256;
 }
 
 template <typename T, int SCHEME, int BC, int TX, int TY, int STEPS>
@@ -283,7 +284,9 @@ int launch_multi(smrt_ctx* c, const T* s, T* d, const smrt::Geom& g,
                  const smrt::Coef<typename smrt::Storage<T>::C>& k, int ntiles)
 {
     constexpr int NT = multi_threads(STEPS, TX, TY);
-    if constexpr (STEPS == 4)
+    if constexpr (STEPS == 5)
+        smrt::stream_collide_x5<T, SCHEME, BC, TX, TY, NT><<<ntiles, NT, 0, c->stream>>>(s, d, g, k);
+    else if constexpr (STEPS == 4)
         smrt::stream_collide_x4<T, SCHEME, BC, TX, TY, NT><<<ntiles, NT, 0, c->stream>>>(s, d, g, k);
     else if constexpr (STEPS == 3)
         smrt::stream_collide_x3<T, SCHEME, BC, TX, TY, NT><<<ntiles, NT, 0, c->stream>>>(s, d, g, k);
@@ -292,7 +295,7 @@ int launch_multi(smrt_ctx* c, const T* s, T* d, const smrt::Geom& g,
     return SMRT_OK;
 }
 
-// One launch of the STEPS-step kernel (STEPS = 2, 3, 4).
+// One launch of the STEPS-step kernel (STEPS = 2 .. 5).
 template <typename T, int STEPS, int TX, int TY> int launch_multi_tile(smrt_ctx* c, const void* src, void* dst)
 {
     using C = typename smrt::Storage<T>::C;
@@ -356,10 +359,13 @@ template <typename T, int STEPS> int launch_step34(smrt_ctx* c, int rows, const 
     }
 }
 
-// One launch of k = 2, 3 or 4 time steps with a 64 x rows tile (2: also
-// cols x rows with cols = 128); FP32 and 16-bit storage only.
+// One launch of k = 2 .. 5 time steps with a 64 x rows tile (2: also
+// cols x rows with cols = 128; 5: 64 x 16 or 64 x 22); FP32 and 16-bit
+// storage only.
 template <typename T> int launch_k(smrt_ctx* c, int k, int cols, int rows, const void* src, void* dst)
 {
+    if (k == 5)
+        return rows == 22 ? launch_multi_tile<T, 5, 64, 22>(c, src, dst) : launch_multi_tile<T, 5, 64, 16>(c, src, dst);
     if (k == 4) return launch_step34<T, 4>(c, rows, src, dst);
     if (k == 3) return launch_step34<T, 3>(c, rows, src, dst);
     return launch_step2<T>(c, cols, rows, src, dst);
@@ -491,12 +497,14 @@ int smrt_create(const smrt_params* p, void* dev_ws, size_t ws_bytes, smrt_ctx** 
         // lattice allows (512 measured best on 4096^2, within 1-2% of 256).
         // FP32 and 16-bit storage take the LDS-blocked kernels, tiles in XCD
         // panels of 16 tile columns, 512 threads per workgroup.  Measured on
-        // 512^2 .. 4096^2: FP32 and 16-bit storage four steps per launch,
-        // with 64 x 26 tiles while that gives >= 1024 workgroups (the tall
-        // tile leaves fewer idle lanes on the rings), else 64 x 16 while that
-        // gives >= 256; smaller lattices two steps with 64 x 32 tiles while
-        // that gives >= 512 workgroups, else with 64 x 4.  Periodic lattices
-        // need room for the rings.
+        // 512^2 .. 4096^2: FP32 storage five steps per launch, with 64 x 22
+        // tiles while that gives >= 1024 workgroups, else 64 x 16 while that
+        // gives >= 256; 16-bit storage four steps, with 64 x 26 tiles while
+        // that gives >= 1024 workgroups (the tall tile leaves fewer idle
+        // lanes on the rings), else 64 x 16 while that gives >= 256; smaller
+        // lattices two steps with 64 x 32 tiles while that gives >= 512
+        // workgroups, else with 64 x 4.  Periodic lattices need room for the
+        // rings.
         if (p->storage == SMRT_F64) {
             // FP64 (twice the LDS per node): four steps with 64 x 10 tiles
             // (80.6 KB of LDS, two workgroups per CU), measured best on
@@ -515,11 +523,12 @@ int smrt_create(const smrt_params* p, void* dev_ws, size_t ws_bytes, smrt_ctx** 
             };
             c->fused_cols = 64;
             c->panel = 16;
-            if (tiles(26) >= 1024 && fits(4, 26)) {
-                c->fused = 4;
-                c->fused_rows = 26;
-            } else if (tiles(16) >= 256 && fits(4, 16)) {
-                c->fused = 4;
+            const int deep = p->storage == SMRT_F32 ? 5 : 4, tall = p->storage == SMRT_F32 ? 22 : 26;
+            if (tiles(tall) >= 1024 && fits(deep, tall)) {
+                c->fused = deep;
+                c->fused_rows = tall;
+            } else if (tiles(16) >= 256 && fits(deep, 16)) {
+                c->fused = deep;
                 c->fused_rows = 16;
             } else {
                 c->fused_rows = tiles(32) >= 512 ? 32 : 4;
@@ -619,17 +628,17 @@ int smrt_step(smrt_ctx* c, int64_t n)
     int64_t left = n;
     while (left > 0) {
         // the largest launch that fits: fused steps, then one shorter launch
-        // (three steps with the same tile; two steps with the same tile, or
-        // 64 x 16 / 64 x 8 after a deeper mode, whose rings need at least as
-        // much room on a periodic lattice)
+        // with 64 x 16 tiles (64 x 8 after a mode with shorter tiles, and for
+        // FP64 storage), whose rings need no more room on a periodic lattice
+        // than the deeper mode's
         const int k = (int)std::min<int64_t>(c->fused, left);
         const void* src = c->buffer(c->cur);
         void* dst = c->buffer(c->cur ^ 1);
         int rc;
         if (k == 1)
             rc = dispatch_step(c, src, dst);
-        else if (k == 2 && c->fused > 2)
-            rc = dispatch_multi(c, 2, 64, c->fused_rows >= 16 ? 16 : 8, src, dst); // FP64: 64 x 8
+        else if (k < c->fused)
+            rc = dispatch_multi(c, k, 64, c->fused_rows >= 16 ? 16 : 8, src, dst);
         else
             rc = dispatch_multi(c, k, c->fused_cols, c->fused_rows, src, dst);
         if (rc) return rc;
@@ -714,7 +723,7 @@ int smrt_set_launch(smrt_ctx* c, int32_t bx, int32_t by, int32_t rows)
 int smrt_set_steps_per_launch(smrt_ctx* c, int32_t steps, int32_t tile_cols, int32_t tile_rows)
 {
     if (!c) return fail(SMRT_EINVAL, "context is NULL");
-    if (steps < 1 || steps > 4) return fail(SMRT_EINVAL, "steps per launch must be 1 .. 4 (got %d)", steps);
+    if (steps < 1 || steps > 5) return fail(SMRT_EINVAL, "steps per launch must be 1 .. 5 (got %d)", steps);
     if (steps == 1) { // one step per launch has no tile: keep the multi-step one
         c->fused = 1;
         return SMRT_OK;
@@ -723,7 +732,10 @@ int smrt_set_steps_per_launch(smrt_ctx* c, int32_t steps, int32_t tile_cols, int
     if (tile_rows == 0) tile_rows = steps >= 3 && c->p.storage != SMRT_F64 ? 16 : 8;
     bool ok;
     if (c->p.storage == SMRT_F64)
-        ok = tile_cols == 64 && (tile_rows == 8 || (steps == 4 && tile_rows == 10) || (steps == 2 && tile_rows == 4));
+        ok = steps <= 4 && tile_cols == 64 &&
+             (tile_rows == 8 || (steps == 4 && tile_rows == 10) || (steps == 2 && tile_rows == 4));
+    else if (steps == 5)
+        ok = tile_cols == 64 && (tile_rows == 16 || tile_rows == 22);
     else
         ok = steps >= 3 ? tile_cols == 64 && (tile_rows == 8 || tile_rows == 16 || tile_rows == 24 || tile_rows == 26)
                         : (tile_cols == 64 && (tile_rows == 4 || tile_rows == 8 || tile_rows == 16 || tile_rows == 32)) ||

@@ -337,9 +337,11 @@ class Solver:
         _check(load().smrt_set_launch(self._ctx, int(bx), int(by), int(rows)))
 
     def set_steps_per_launch(self, steps, tile_rows=0, tile_cols=0):
-        """1, or 2 .. 4 for the LDS-blocked kernels (FP32/16-bit storage);
+        """1, or 2 .. 5 for the LDS-blocked kernels (FP64 storage: 2 .. 4);
         two-step tiles 64 x {4, 8, 16, 32} or 128 x {4, 8} (0 = 64 x 8),
-        three- and four-step tiles 64 x {8, 16, 24, 26} (0 = 64 x 16)."""
+        three- and four-step tiles 64 x {8, 16, 24, 26} (0 = 64 x 16),
+        five-step tiles 64 x {16, 22} (0 = 64 x 16); FP64 storage 64 x 8
+        (also 64 x 4 for two steps, 64 x 10 for four)."""
         _check(load().smrt_set_steps_per_launch(self._ctx, int(steps), int(tile_cols), int(tile_rows)))
 
     def set_tile_order(self, panel_cols):

@@ -449,15 +449,41 @@ def test_multi_step_kernel_equals_single_steps(smrt, storage, boundary, scheme, 
         assert np.array_equal(outs[0], outs[1])
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("boundary", ["periodic", "cavity"])
+@pytest.mark.parametrize("scheme", ["srt", "smrt", "trt"])
+@pytest.mark.parametrize("tile", [(64, 16), (64, 22)])
+def test_five_step_kernel_equals_single_steps(smrt, storage, boundary, scheme, tile):
+    """Five steps per launch (four nested LDS rings): bitwise equal to one-step
+    launches on a ragged lattice; 41, 43 and 44 steps end with launches of 1,
+    3 and 4 steps."""
+    nx, ny = 203, 77
+    f0 = inputs.perturbed_populations(nx, ny, eps=0.03, seed=5)
+    u = 0.1 if boundary == "cavity" else 0.0
+    for steps in (41, 43, 44):
+        outs = []
+        for spl in (1, 5):
+            with smrt.Solver(nx, ny, scheme=scheme, boundary=boundary, storage=storage, tau=0.56,
+                             u_lid=u, tau_s=0.9) as s:
+                s.set_populations(to_dev(f0, torch.float64))
+                s.set_steps_per_launch(spl, tile_rows=tile[1], tile_cols=tile[0])
+                s.step(steps)
+                assert s.steps_done == steps
+                outs.append(s.populations(torch.float64).cpu().numpy())
+        assert np.array_equal(outs[0], outs[1])
+
+
 @pytest.mark.parametrize("nx,ny", [(3, 3), (5, 70), (13, 21), (64, 64), (65, 9)])
-@pytest.mark.parametrize("multi", [3, 4])
+@pytest.mark.parametrize("multi", [3, 4, 5])
 @pytest.mark.parametrize("storage", ["f32", "f64"])
 def test_multi_step_kernel_small_cavities(smrt, nx, ny, multi, storage):
+    if storage == "f64" and multi == 5:
+        pytest.skip("FP64 storage runs at most four steps per launch")
     outs = []
     for spl in (1, multi):
         with smrt.Solver(nx, ny, scheme="smrt", boundary="cavity", storage=storage, tau=0.6,
                          u_lid=0.1) as s:
-            s.set_steps_per_launch(spl, tile_rows=8)
+            s.set_steps_per_launch(spl, tile_rows=16 if spl == 5 else 8)
             s.step(31)
             outs.append(s.populations(torch.float64).cpu().numpy())
     assert np.array_equal(outs[0], outs[1])
@@ -491,18 +517,25 @@ def test_three_step_kernel_rejects_unsupported(smrt):
         with pytest.raises(smrt.SmrtError):
             s.set_steps_per_launch(4)                  # periodic, nx < 64 + 6
         with pytest.raises(smrt.SmrtError):
-            s.set_steps_per_launch(5)
+            s.set_steps_per_launch(5)                  # periodic, nx < 64 + 8
     with smrt.Solver(70, 100, scheme="smrt", boundary="periodic", storage="f32", tau=0.7) as s:
         s.set_steps_per_launch(4)                      # 70 >= 64 + 6, 100 >= 16 + 6
+    with smrt.Solver(72, 30, scheme="smrt", boundary="periodic", storage="f32", tau=0.7) as s:
+        s.set_steps_per_launch(5, tile_rows=22)        # 72 >= 64 + 8, 30 >= 22 + 8
+        with pytest.raises(smrt.SmrtError):
+            s.set_steps_per_launch(5, tile_rows=26)    # tile not offered
+        with pytest.raises(smrt.SmrtError):
+            s.set_steps_per_launch(6)
 
 
 @pytest.mark.parametrize("n,boundary,steps,storage", [(4096, "periodic", 402, "f32"), (1024, "cavity", 4001, "f32"),
                                                      (1024, "cavity", 1001, "f64"), (2048, "periodic", 402, "f16")])
 def test_default_launch_long_run_bitwise(smrt, n, boundary, steps, storage):
-    """The default launch configuration (four steps per launch: 64 x 26 tiles on
-    4096^2 and 2048^2, 64 x 16 on 1024^2, 64 x 10 for FP64 storage) over many
-    launches at the benchmark sizes: populations bitwise those of one step per
-    launch, compared on the device."""
+    """The default launch configuration (FP32 five steps per launch: 64 x 22
+    tiles on 4096^2, 64 x 16 on 1024^2; FP16 four steps with 64 x 26 tiles;
+    FP64 four steps with 64 x 10) over many launches at the benchmark sizes,
+    with a shorter launch at the end: populations bitwise those of one step
+    per launch, compared on the device."""
     outs = []
     for default in (True, False):
         with smrt.Solver(n, n, scheme="smrt", boundary=boundary, storage=storage, tau=0.6,
@@ -510,7 +543,7 @@ def test_default_launch_long_run_bitwise(smrt, n, boundary, steps, storage):
             if boundary == "periodic":
                 s.init_fields(*(to_dev(a) for a in inputs.taylor_green(n, n)))
             if default:
-                assert s.steps_per_launch == 4
+                assert s.steps_per_launch == (5 if storage == "f32" else 4)
             else:
                 s.set_steps_per_launch(1)
             s.step(steps)
