@@ -252,7 +252,7 @@ size_t smrt_batch_workspace_bytes(const smrt_batch_params* p);
  * running.  dev_ws as for smrt_create (caller-owned or NULL).  The library
  * also allocates small device tables, a pinned host buffer and one private
  * capture stream (default priority).  Default launch: 64 x 16 tiles with
- * four time steps per launch (FP32 storage) or three (16-bit storage); FP64
+ * five time steps per launch (FP32 storage) or three (16-bit storage); FP64
  * storage one step with 64 x 4 blocks; one workgroup per tile.  Errors as for
  * smrt_create, per cavity; also SMRT_EINVAL when the tile table would exceed
  * 2^31 - 1 entries. */
@@ -274,8 +274,9 @@ int smrt_batch_run(smrt_batch* b, double tol, int64_t window, int64_t max_steps,
 /* Chooses the tile shape (bx, by), the time steps per launch and the number
  * of resident workgroups of the batch kernel by timing `steps` real steps (an
  * even number >= 2) of each candidate (the one-step shapes, and except for
- * FP64 storage the two-step kernel with 64 x 4, 64 x 8 and 64 x 16 tiles and
- * the three- and four-step kernels with 64 x 8 and 64 x 16 tiles); keeps the
+ * FP64 storage the two-step kernel with 64 x 4, 64 x 8 and 64 x 16 tiles,
+ * the three- and four-step kernels with 64 x 8 and 64 x 16 tiles and the
+ * five-step kernel with 64 x 16 tiles); keeps the
  * fastest.
  * chosen (host [3], may be NULL) receives bx, by and the grid size;
  * smrt_batch_steps_per_launch reports the steps per launch.  The trial steps
@@ -298,7 +299,7 @@ int64_t smrt_batch_steps_done(const smrt_batch* b);
 /* Number of cavities still running. */
 int32_t smrt_batch_running(const smrt_batch* b);
 
-/* Time steps per launch in use (1 .. 4); -1 for b == NULL. */
+/* Time steps per launch in use (1 .. 5); -1 for b == NULL. */
 int32_t smrt_batch_steps_per_launch(const smrt_batch* b);
 
 /* Frees what the library allocated (not the caller's workspace). NULL: no-op. */

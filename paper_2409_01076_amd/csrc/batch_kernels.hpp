@@ -101,8 +101,11 @@ __global__ void __launch_bounds__(1024) batch_stream_collide(const CavityDesc* _
     }
 }
 
+// Every multi-step kernel below is built for two resident workgroups per CU
+// (the LDS allows two): NT / 128 waves per SIMD, which caps the registers.
+//
 // S time steps of every listed tile per launch: the batch form of the
-// multi-step kernels (stream_collide_x2 / _x3 / _x4, same phases through LDS), for
+// multi-step kernels (stream_collide_x2 .. _x5, same phases through LDS), for
 // tiles of TX x TY nodes and NT threads.  Cavity walls need no wrap, so any
 // size works.
 template <typename T, int SCHEME, int TX, int TY, int NT, int S>
@@ -136,7 +139,7 @@ __device__ __forceinline__ void batch_multi(const CavityDesc* __restrict__ cav, 
 }
 
 template <typename T, int SCHEME, int TX, int TY, int NT>
-__global__ void __launch_bounds__(NT) batch_stream_collide_x2(const CavityDesc* __restrict__ cav,
+__global__ void __launch_bounds__(NT, NT / 128) batch_stream_collide_x2(const CavityDesc* __restrict__ cav,
                                                               const int2* __restrict__ tiles,
                                                               const int* __restrict__ ntiles_p,
                                                               T* __restrict__ base, int parity)
@@ -146,7 +149,7 @@ __global__ void __launch_bounds__(NT) batch_stream_collide_x2(const CavityDesc* 
 }
 
 template <typename T, int SCHEME, int TX, int TY, int NT>
-__global__ void __launch_bounds__(NT) batch_stream_collide_x3(const CavityDesc* __restrict__ cav,
+__global__ void __launch_bounds__(NT, NT / 128) batch_stream_collide_x3(const CavityDesc* __restrict__ cav,
                                                               const int2* __restrict__ tiles,
                                                               const int* __restrict__ ntiles_p,
                                                               T* __restrict__ base, int parity)
@@ -156,13 +159,23 @@ __global__ void __launch_bounds__(NT) batch_stream_collide_x3(const CavityDesc* 
 }
 
 template <typename T, int SCHEME, int TX, int TY, int NT>
-__global__ void __launch_bounds__(NT) batch_stream_collide_x4(const CavityDesc* __restrict__ cav,
+__global__ void __launch_bounds__(NT, NT / 128) batch_stream_collide_x4(const CavityDesc* __restrict__ cav,
                                                               const int2* __restrict__ tiles,
                                                               const int* __restrict__ ntiles_p,
                                                               T* __restrict__ base, int parity)
 {
     __shared__ MultiTile<T, TX, TY, 4> sh;
     batch_multi<T, SCHEME, TX, TY, NT, 4>(cav, tiles, ntiles_p, base, parity, sh);
+}
+
+template <typename T, int SCHEME, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT, NT / 128) batch_stream_collide_x5(const CavityDesc* __restrict__ cav,
+                                                              const int2* __restrict__ tiles,
+                                                              const int* __restrict__ ntiles_p,
+                                                              T* __restrict__ base, int parity)
+{
+    __shared__ MultiTile<T, TX, TY, 5> sh;
+    batch_multi<T, SCHEME, TX, TY, NT, 5>(cav, tiles, ntiles_p, base, parity, sh);
 }
 
 // Per-tile FP64 partial sums (|u - u_snap|^2, |u|^2, rho - 1, non-finite

@@ -226,10 +226,10 @@ int upload_tables(smrt_batch* b)
     return SMRT_OK;
 }
 
-// Threads per multi-step workgroup, as for single lattices: 768 for
-// four-step tiles (64 x 8 and 64 x 16), 512 for other 64 x 16 tiles, 256 for
-// smaller.
-constexpr int multi_threads(int steps, int ty) { return steps == 4 && ty >= 8 ? 768 : ty >= 16 ? 512 : 256; }
+// Threads per multi-step workgroup, as for single lattices: 768 for four-
+// and five-step tiles (64 x 8 and 64 x 16), 512 for other 64 x 16 tiles, 256
+// for smaller.
+constexpr int multi_threads(int steps, int ty) { return steps >= 4 && ty >= 8 ? 768 : ty >= 16 ? 512 : 256; }
 
 template <typename T, int SCHEME, int TY>
 void launch_two_tile(smrt_batch* b, hipStream_t s, int parity, dim3 grid)
@@ -255,12 +255,25 @@ void launch_four_tile(smrt_batch* b, hipStream_t s, int parity, dim3 grid)
         b->desc(), b->table(), b->ntiles_dev(), reinterpret_cast<T*>(b->state()), parity);
 }
 
-// One launch of k time steps (k = 2, 3, 4: 64 x shape.by tiles; the tile
+template <typename T, int SCHEME, int TY>
+void launch_five_tile(smrt_batch* b, hipStream_t s, int parity, dim3 grid)
+{
+    constexpr int NT = multi_threads(5, TY);
+    smrt::batch_stream_collide_x5<T, SCHEME, 64, TY, NT><<<grid, NT, 0, s>>>(
+        b->desc(), b->table(), b->ntiles_dev(), reinterpret_cast<T*>(b->state()), parity);
+}
+
+// One launch of k time steps (k = 2 .. 5: 64 x shape.by tiles; the tile
 // table is built for that shape, so a shorter remainder launch uses the same
 // table).
 template <typename T, int SCHEME> void launch_typed_scheme(smrt_batch* b, hipStream_t s, int parity, int k)
 {
     dim3 grid((unsigned)std::max(b->grid, 1));
+    if (k == 5) {
+        if (b->shape.by == 16) launch_five_tile<T, SCHEME, 16>(b, s, parity, grid);
+        else launch_five_tile<T, SCHEME, 8>(b, s, parity, grid);
+        return;
+    }
     if (k == 4) {
         if (b->shape.by == 16) launch_four_tile<T, SCHEME, 16>(b, s, parity, grid);
         else launch_four_tile<T, SCHEME, 8>(b, s, parity, grid);
@@ -291,7 +304,7 @@ template <typename T> void launch_step_typed(smrt_batch* b, hipStream_t s, int p
     }
 }
 
-// One launch of k = 1 .. 4 time steps (FP64 storage has only the one-step
+// One launch of k = 1 .. 5 time steps (FP64 storage has only the one-step
 // kernel).
 void launch_step(smrt_batch* b, hipStream_t s, int parity, int k)
 {
@@ -479,10 +492,11 @@ int smrt_batch_create(const smrt_batch_params* p, void* dev_ws, size_t ws_bytes,
             return hip_fail(e, "hipMemsetAsync");
         }
         // Default launch: one pass over the table per launch; FP64 one step
-        // per launch with 64 x 4 tiles, other storage 64 x 16 tiles with four
-        // steps per launch (FP32) or three (16-bit), as for single lattices.
+        // per launch with 64 x 4 tiles, other storage 64 x 16 tiles with five
+        // steps per launch (FP32) or three (16-bit); the autotuner chose five
+        // steps with 64 x 16 tiles for FP32 batches of 16 to 256 cavities.
         b->shape = p->storage == SMRT_F64 ? kShapes[0] : smrt::BatchLaunch{64, 16};
-        b->multi = p->storage == SMRT_F64 ? 1 : p->storage == SMRT_F32 ? 4 : 3;
+        b->multi = p->storage == SMRT_F64 ? 1 : p->storage == SMRT_F32 ? 5 : 3;
         int64_t total_tiles = 0;
         for (const auto& c : b->plan.desc) total_tiles += tiles_of(c.nx, c.ny, b->shape);
         b->grid = (int)total_tiles; // at most the plan's max_tiles
@@ -583,11 +597,12 @@ int smrt_batch_autotune(smrt_batch* b, int32_t steps, int32_t* chosen)
     int best_multi = b->multi;
     int rc = SMRT_OK;
     // Candidates: every one-step shape, then (except for FP64) the two-step
-    // kernel with 64 x 4, 64 x 8 and 64 x 16 tiles and the three- and
-    // four-step kernels with 64 x 8 and 64 x 16 tiles; times are per time step.
-    static const int kMultiSteps[] = {2, 2, 2, 3, 3, 4, 4};
-    static const int kMultiRows[] = {4, 8, 16, 8, 16, 8, 16};
-    const int n_multi = b->p.storage == SMRT_F64 ? 0 : 7;
+    // kernel with 64 x 4, 64 x 8 and 64 x 16 tiles, the three- and four-step
+    // kernels with 64 x 8 and 64 x 16 tiles and the five-step kernel with
+    // 64 x 16 tiles; times are per time step.
+    static const int kMultiSteps[] = {2, 2, 2, 3, 3, 4, 4, 5};
+    static const int kMultiRows[] = {4, 8, 16, 8, 16, 8, 16, 16};
+    const int n_multi = b->p.storage == SMRT_F64 ? 0 : 8;
     for (int s = 0; s < kNumShapes + n_multi && rc == SMRT_OK; ++s) {
         const int multi = s >= kNumShapes ? kMultiSteps[s - kNumShapes] : 1;
         b->shape = multi > 1 ? smrt::BatchLaunch{64, kMultiRows[s - kNumShapes]} : kShapes[s];
