@@ -60,12 +60,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget")
     ap.add_argument("--workload", default="tg",
-                    choices=["tg", "cavity", "precision", "batch", "warmstart"],
+                    choices=["tg", "cavity", "precision", "batch", "warmstart", "small"],
                     help="tg: periodic Taylor-Green throughput (default); cavity: lid-driven "
                          "cavity run from the cold start to the steady-state residual; "
                          "precision: one cavity in every storage type against FP64; "
                          "batch: many cavities of uneven size and Re run together to steady; "
-                         "warmstart: learned warm start against the cold start")
+                         "warmstart: learned warm start against the cold start; "
+                         "small: the 64^2 FP64 cavity at Re 100, eager and graph-captured")
     ap.add_argument("--train", type=int, default=200, help="warmstart: training cavities")
     ap.add_argument("--held-out", type=int, default=50, help="warmstart: evaluation cavities")
     ap.add_argument("--epochs", type=int, default=120, help="warmstart: training epochs")
@@ -173,6 +174,61 @@ def cpu_model():
     except OSError:
         pass
     return "unknown"
+
+
+def small_cavity(args):
+    """The 64 x 64 FP64 cavity at Re = 100 (U = 0.1), 2000 steps, SmrtLBM and
+    SRT: 4096 nodes, so each launch is bound by launch latency, not by the
+    GPU.  Times the steps issued one call at a time and replayed from a
+    captured HIP graph (each graph holds an even number of launches, so a
+    replay leaves the buffer parity as capture found it) and checks that both
+    end bitwise equal."""
+    import torch
+
+    from paper_2409_01076_amd import smrt
+
+    n, steps, per_graph = 64, 2000, 200
+    out = {"workload": "lid-driven cavity 64x64, Re=100, U=0.1, f64 storage, 2000 steps from the cold start",
+           "results": {}}
+    side = torch.cuda.Stream()
+    for scheme in ("smrt", "srt"):
+        with torch.cuda.stream(side):
+            warm = smrt.Solver(n, n, scheme=scheme, storage="f64", re=100.0, u_lid=0.1)
+            warm.step(per_graph)
+            warm.close()
+            eager = smrt.Solver(n, n, scheme=scheme, storage="f64", re=100.0, u_lid=0.1)
+            replay = smrt.Solver(n, n, scheme=scheme, storage="f64", re=100.0, u_lid=0.1)
+        spl = eager.steps_per_launch
+        if (per_graph // spl) % 2 or per_graph % spl:
+            raise RuntimeError("a graph of %d steps needs an even number of %d-step launches" % (per_graph, spl))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(side)
+        with torch.cuda.stream(side):
+            eager.step(steps)
+        e1.record(side)
+        torch.cuda.synchronize()
+        eager_us = e0.elapsed_time(e1) * 1e3 / steps
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            replay.step(per_graph)
+        torch.cuda.synchronize()
+        e0.record(side)
+        with torch.cuda.stream(side):
+            for _ in range(steps // per_graph):
+                g.replay()
+        e1.record(side)
+        torch.cuda.synchronize()
+        graph_us = e0.elapsed_time(e1) * 1e3 / steps
+        same = bool(torch.equal(eager.populations(torch.float64), replay.populations(torch.float64)))
+        out["results"][scheme] = {"steps_per_launch": spl, "eager_us_per_step": round(eager_us, 3),
+                                  "graph_us_per_step": round(graph_us, 3),
+                                  "mlups_eager": round(n * n / eager_us, 1), "mlups_graph": round(n * n / graph_us, 1),
+                                  "graph_equals_eager": same}
+        del g
+        eager.close()
+        replay.close()
+    print(json.dumps(out))
 
 
 def cavity_to_steady(args):
@@ -458,6 +514,9 @@ def main():
         return
     if args.workload == "warmstart":
         warm_start_study(args)
+        return
+    if args.workload == "small":
+        small_cavity(args)
         return
 
     from paper_2409_01076_amd import inputs, smrt

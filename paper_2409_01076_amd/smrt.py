@@ -5,6 +5,7 @@ kernels of ``libsmrt.so``.  PyTorch provides device memory (the workspace and
 the field/population tensors) and the stream.  There is no CPU fallback: on a
 machine without the built library or without a GPU, creating a solver raises.
 """
+import contextlib
 import ctypes
 import os
 
@@ -175,6 +176,22 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
+@contextlib.contextmanager
+def _caller_order(own, device):
+    """For a call that reads or writes caller tensors on an object's own
+    stream: the object's stream first waits for the caller's current stream
+    (inputs written, memory free), and afterwards the caller's stream waits
+    for the object's (results visible to the caller's next operations).  No
+    effect when the two are the same stream."""
+    cur = torch.cuda.current_stream(device)
+    if cur.cuda_stream == own.cuda_stream:
+        yield
+        return
+    own.wait_stream(cur)
+    yield
+    cur.wait_stream(own)
+
+
 class Solver:
     """One lattice on one GPU.
 
@@ -182,7 +199,10 @@ class Solver:
     ``boundary`` in {'cavity', 'periodic'}, ``storage`` in {'f64', 'f32',
     'f16', 'bf16'}; give ``tau`` directly or ``re`` (then tau = 3 U N / Re + 1/2).
     The workspace is a torch uint8 tensor on ``device``; work goes to the
-    current torch stream of that device at construction time.
+    current torch stream of that device at construction time.  Calls that take
+    or return tensors are ordered against the caller's current stream, so the
+    two streams may differ (e.g. a solver created on a side stream for graph
+    capture).
     """
 
     def __init__(self, nx, ny, scheme="smrt", boundary="cavity", storage="f32", tau=None,
@@ -256,17 +276,20 @@ class Solver:
         if any(t.dtype != dtype for t in given):
             raise ValueError("rho, ux, uy must share one dtype")
         s = (self.ny, self.nx)
-        _check(load().smrt_init_fields(self._ctx, _ptr(self._io(rho, s)), _ptr(self._io(ux, s)),
-                                       _ptr(self._io(uy, s)), _IO_DTYPES[dtype]))
+        with _caller_order(self.stream, self.device):
+            _check(load().smrt_init_fields(self._ctx, _ptr(self._io(rho, s)), _ptr(self._io(ux, s)),
+                                           _ptr(self._io(uy, s)), _IO_DTYPES[dtype]))
 
     def set_populations(self, f):
         """Post-collision populations f, tensor (9, ny, nx) float32/float64."""
         f = self._io(f, (9, self.ny, self.nx))
-        _check(load().smrt_set_populations(self._ctx, _ptr(f), _IO_DTYPES[f.dtype]))
+        with _caller_order(self.stream, self.device):
+            _check(load().smrt_set_populations(self._ctx, _ptr(f), _IO_DTYPES[f.dtype]))
 
     def populations(self, dtype=torch.float64):
         out = torch.empty((9, self.ny, self.nx), dtype=dtype, device=self.device)
-        _check(load().smrt_get_populations(self._ctx, _ptr(out), _IO_DTYPES[dtype]))
+        with _caller_order(self.stream, self.device):
+            _check(load().smrt_get_populations(self._ctx, _ptr(out), _IO_DTYPES[dtype]))
         return out
 
     def step(self, n=1):
@@ -287,8 +310,9 @@ class Solver:
         dtype = given[0].dtype
         if any(t.dtype != dtype for t in given):
             raise ValueError("rho, ux, uy must share one dtype")
-        _check(load().smrt_moments(self._ctx, _ptr(self._io(rho, s)), _ptr(self._io(ux, s)),
-                                   _ptr(self._io(uy, s)), _IO_DTYPES[dtype]))
+        with _caller_order(self.stream, self.device):
+            _check(load().smrt_moments(self._ctx, _ptr(self._io(rho, s)), _ptr(self._io(ux, s)),
+                                       _ptr(self._io(uy, s)), _IO_DTYPES[dtype]))
         return rho, ux, uy
 
     def residual(self):
@@ -455,8 +479,9 @@ class Batch:
     def moments(self, index, dtype=torch.float64):
         s = (self.ny[index], self.nx[index])
         rho, ux, uy = (torch.empty(s, dtype=dtype, device=self.device) for _ in range(3))
-        _check(load().smrt_batch_moments(self._ctx, int(index), _ptr(rho), _ptr(ux), _ptr(uy),
-                                         _IO_DTYPES[dtype]))
+        with _caller_order(self.stream, self.device):
+            _check(load().smrt_batch_moments(self._ctx, int(index), _ptr(rho), _ptr(ux), _ptr(uy),
+                                             _IO_DTYPES[dtype]))
         return rho, ux, uy
 
     def init_fields(self, index, rho=None, ux=None, uy=None):
@@ -466,8 +491,9 @@ class Batch:
         for t in given:
             if t.dtype != dtype or tuple(t.shape) != s or not t.is_contiguous() or t.device != self.device:
                 raise ValueError("fields must be contiguous %s tensors of shape %s" % (dtype, s))
-        _check(load().smrt_batch_init_fields(self._ctx, int(index), _ptr(rho), _ptr(ux), _ptr(uy),
-                                             _IO_DTYPES[dtype]))
+        with _caller_order(self.stream, self.device):
+            _check(load().smrt_batch_init_fields(self._ctx, int(index), _ptr(rho), _ptr(ux), _ptr(uy),
+                                                 _IO_DTYPES[dtype]))
 
 
 class MLP:
@@ -524,11 +550,13 @@ class MLP:
     def set_params(self, params, fourier_matrix):
         self._f32(params, (self.param_count,))
         self._f32(fourier_matrix, (self.fourier, 3))
-        _check(load().smrt_mlp_set_params(self._ctx, _ptr(params), _ptr(fourier_matrix)))
+        with _caller_order(self.stream, self.device):
+            _check(load().smrt_mlp_set_params(self._ctx, _ptr(params), _ptr(fourier_matrix)))
 
     def get_params(self):
         out = torch.empty(self.param_count, dtype=torch.float32, device=self.device)
-        _check(load().smrt_mlp_get_params(self._ctx, _ptr(out)))
+        with _caller_order(self.stream, self.device):
+            _check(load().smrt_mlp_get_params(self._ctx, _ptr(out)))
         return out
 
     def forward(self, points, out=None):
@@ -536,24 +564,28 @@ class MLP:
         self._f32(points, (n, 3))
         if out is None:
             out = torch.empty((n, self.outputs), dtype=torch.float32, device=self.device)
-        _check(load().smrt_mlp_forward(self._ctx, _ptr(points), int(n), _ptr(self._f32(out, (n, self.outputs)))))
+        with _caller_order(self.stream, self.device):
+            _check(load().smrt_mlp_forward(self._ctx, _ptr(points), int(n),
+                                           _ptr(self._f32(out, (n, self.outputs)))))
         return out
 
     def gradient(self, points, target):
         n = points.shape[0]
         grad = torch.empty(self.param_count, dtype=torch.float32, device=self.device)
         loss = ctypes.c_double()
-        _check(load().smrt_mlp_gradient(self._ctx, _ptr(self._f32(points, (n, 3))),
-                                        _ptr(self._f32(target, (n, self.outputs))), int(n), _ptr(grad),
-                                        ctypes.byref(loss)))
+        with _caller_order(self.stream, self.device):
+            _check(load().smrt_mlp_gradient(self._ctx, _ptr(self._f32(points, (n, 3))),
+                                            _ptr(self._f32(target, (n, self.outputs))), int(n), _ptr(grad),
+                                            ctypes.byref(loss)))
         return loss.value, grad
 
     def train_step(self, points, target, lr, want_loss=False):
         n = points.shape[0]
         loss = ctypes.c_double() if want_loss else None
-        _check(load().smrt_mlp_train_step(self._ctx, _ptr(self._f32(points, (n, 3))),
-                                          _ptr(self._f32(target, (n, self.outputs))), int(n),
-                                          float(lr), ctypes.byref(loss) if want_loss else None))
+        with _caller_order(self.stream, self.device):
+            _check(load().smrt_mlp_train_step(self._ctx, _ptr(self._f32(points, (n, 3))),
+                                              _ptr(self._f32(target, (n, self.outputs))), int(n),
+                                              float(lr), ctypes.byref(loss) if want_loss else None))
         return loss.value if want_loss else None
 
 

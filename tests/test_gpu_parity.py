@@ -580,3 +580,30 @@ def test_two_step_kernel_rejects_unsupported(smrt):
             s.set_steps_per_launch(3, tile_rows=10)
         with pytest.raises(smrt.SmrtError):
             s.set_steps_per_launch(5)
+
+
+@pytest.mark.parametrize("n,storage", [(96, "f32"), (64, "f64"), (600, "f32")])
+def test_graph_captured_steps_match_eager(smrt, n, storage):
+    """Steps replayed from a captured HIP graph (an even number of launches, so
+    a replay leaves the buffer parity as capture found it) equal the same
+    steps issued one call at a time, replay after replay, with other eager
+    work and synchronizations between the replays."""
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        eager = smrt.Solver(n, n, scheme="smrt", storage=storage, re=300.0, u_lid=0.1)
+        replay = smrt.Solver(n, n, scheme="smrt", storage=storage, re=300.0, u_lid=0.1)
+    per_graph = 2 * eager.steps_per_launch * 7
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        replay.step(per_graph)
+    torch.cuda.synchronize()
+    for r in range(4):
+        with torch.cuda.stream(side):
+            g.replay()
+            eager.step(per_graph)
+        assert float(torch.ones(100_000, device="cuda").sum()) == 100_000.0  # other work, synchronizes
+        torch.cuda.synchronize()
+        assert torch.equal(eager.populations(torch.float64), replay.populations(torch.float64)), r
+    del g
+    eager.close()
+    replay.close()
