@@ -375,9 +375,10 @@ void smrt_mlp_destroy(smrt_mlp* m);
  *   C[s][m][n] = sum_{k in split s} opA(m, k) opB(k, n),
  *   opA(m, k) = trans_a ? A[k lda + m] : A[m lda + k],
  *   opB(k, n) = trans_b ? B[n ldb + k] : B[k ldb + n],
- * A, B bfloat16 bit patterns (device), C FP32 (device, splits blocks of
- * M x ldc).  M and N multiples of 64, K a multiple of 32 * splits; split s
- * covers k in [s K/splits, (s+1) K/splits).  SMRT_EINVAL otherwise.
+ * A, B bfloat16 bit patterns (device, 16-byte aligned), C FP32 (device,
+ * splits blocks of M x ldc).  M and N multiples of 64, K a multiple of
+ * 32 * splits, lda and ldb multiples of 8; split s covers k in
+ * [s K/splits, (s+1) K/splits).  SMRT_EINVAL otherwise.
  * Asynchronous on `stream`. */
 int smrt_gemm_bf16(const uint16_t* A, const uint16_t* B, float* C, int32_t M, int32_t N, int32_t K,
                    int32_t lda, int32_t ldb, int32_t ldc, int32_t trans_a, int32_t trans_b,

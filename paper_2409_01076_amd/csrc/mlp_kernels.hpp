@@ -36,58 +36,111 @@ constexpr int GEMM_THREADS = 256;         // 4 waves, each a 32 x 32 quarter
 //   opA(m, k) = TA ? A[k * lda + m] : A[m * lda + k]
 //   opB(k, n) = TB ? B[n * ldb + k] : B[k * ldb + n],
 // bf16 inputs, FP32 accumulation in v_mfma_f32_16x16x32_bf16.  The host
-// guarantees M % 64 == 0, N % 64 == 0 and k_split % 32 == 0; split s covers
-// k in [s * k_split, (s + 1) * k_split).  Grid: (N/64, M/64, splits).
+// guarantees M % 64 == 0, N % 64 == 0, k_split % 32 == 0, lda % 8 == 0,
+// ldb % 8 == 0 and 16-byte aligned A and B; split s covers k in
+// [s * k_split, (s + 1) * k_split).  Grid: (N/64, M/64, splits).
+//
+// Each K-step stages a 64 x 32 slice of opA and a 32 x 64 slice of opB with
+// one 16-byte load per thread and operand, kept in LDS in the layout of the
+// stored rows (so the LDS writes are 16 bytes too); the next slice's loads
+// are issued before the current slice's matrix-core work.
 //
 // MFMA operand layout (16 x 16 x 32, checked on the device against a host
 // product): lane l holds A[l % 16][8 (l / 16) + i] and B[8 (l / 16) + i][l % 16]
 // for i < 8, and receives D[4 (l / 16) + r][l % 16] for r < 4.
-template <bool TA, bool TB>
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float sigmoid(float z) { return 1.0f / (1.0f + __expf(-z)); }
+
+// What a product does with its result v at (m, n) (EPI_STORE for any split
+// count, the others with one split; rows of Z, A, dZ have stride ldc):
+//   EPI_STORE      C[split][m][n] = v
+//   EPI_BIAS_SILU  hidden layer: Z = v + b[n] (FP32, kept for the backward
+//                  pass), A = silu(Z) = Z sigmoid(Z) (bf16)
+//   EPI_BIAS_OUT   output layer: Y[m][n] = v + b[n] for n < keep ([m][keep])
+//   EPI_SILU_GRAD  input gradient: dZ = v silu'(Z), silu'(z) = sigmoid(z)
+//                  (1 + z (1 - sigmoid(z))) (bf16), Z read
+//   EPI_STORE_DB   weight gradient X^T dZ (opA transposed): as EPI_STORE, and
+//                  the workgroups of the first row block also write the
+//                  column sums of this split's opB rows (the bias gradient's
+//                  partial) to the N floats after the split's M x ldc block
+// Split s writes at C + s * split_stride.
+enum { EPI_STORE = 0, EPI_BIAS_SILU = 1, EPI_BIAS_OUT = 2, EPI_SILU_GRAD = 3, EPI_STORE_DB = 4 };
+struct Epilogue {
+    const float* bias = nullptr;
+    float* z = nullptr;       // EPI_BIAS_SILU: written; EPI_SILU_GRAD: read
+    uint16_t* act = nullptr;  // A (EPI_BIAS_SILU) or dZ (EPI_SILU_GRAD)
+    float* y = nullptr;
+    int keep = 0;
+};
+
+template <bool TA, bool TB, int EPI = EPI_STORE>
 __global__ void __launch_bounds__(GEMM_THREADS) gemm_bf16(const uint16_t* __restrict__ A,
                                                           const uint16_t* __restrict__ B, float* __restrict__ C,
-                                                          int M, int N, int lda, int ldb, int ldc, int k_split)
+                                                          int M, int N, int lda, int ldb, int ldc, int k_split,
+                                                          int64_t split_stride, Epilogue ep)
 {
-    __shared__ uint16_t As[TM][TK + 8]; // +8: stagger rows across LDS banks
-    __shared__ uint16_t Bs[TK][TN + 8];
+    // Rows padded by 8 elements (16 bytes) to stagger them across LDS banks.
+    // opA: [m][k] (TA false) or [k][m] (TA true); opB: [k][n] or [n][k].
+    constexpr int AR = TA ? TK : TM, AC = (TA ? TM : TK) + 8;
+    constexpr int BR = TB ? TN : TK, BC = (TB ? TK : TN) + 8;
+    __shared__ __attribute__((aligned(16))) uint16_t As[AR][AC];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[BR][BC];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m_blk = blockIdx.y * TM, n_blk = blockIdx.x * TN;
-    const int k_beg = blockIdx.z * k_split;
+    const int k_beg = blockIdx.z * k_split, k_end = k_beg + k_split;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    // This thread's 8 elements of each slice: row r and column c8 of the
+    // stored layout (rows of 32 elements: 4 threads a row; of 64: 8).
+    const int ar = TA ? tid >> 3 : tid >> 2, ac = TA ? (tid & 7) * 8 : (tid & 3) * 8;
+    const int br = TB ? tid >> 2 : tid >> 3, bc = TB ? (tid & 3) * 8 : (tid & 7) * 8;
+    const auto a_src = [&](int k0) {
+        return TA ? A + (int64_t)(k0 + ar) * lda + m_blk + ac : A + (int64_t)(m_blk + ar) * lda + k0 + ac;
+    };
+    const auto b_src = [&](int k0) {
+        return TB ? B + (int64_t)(n_blk + br) * ldb + k0 + bc : B + (int64_t)(k0 + br) * ldb + n_blk + bc;
+    };
     f32x4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // EPI_STORE_DB: thread t sums rows 8 (t / 64) .. + 7 of column t % 64 of
+    // every staged opB slice (row order), combined over t / 64 at the end
+    constexpr bool DB = EPI == EPI_STORE_DB;
+    static_assert(!DB || (TA && !TB), "bias-gradient sums need opB stored as [k][n]");
+    const bool db_blk = DB && blockIdx.y == 0;
+    float db = 0.f;
 
-    for (int k0 = k_beg; k0 < k_beg + k_split; k0 += TK) {
-        // Stage the 64 x 32 slice of opA and the 32 x 64 slice of opB: 8
-        // elements per thread each, the fastest index along the stored rows.
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int idx = tid + e * GEMM_THREADS; // 0 .. 2047
-            if (TA) {
-                const int m = idx & (TM - 1), k = idx >> 6; // contiguous along m
-                As[m][k] = A[(int64_t)(k0 + k) * lda + m_blk + m];
-            } else {
-                const int k = idx & (TK - 1), m = idx >> 5; // contiguous along k
-                As[m][k] = A[(int64_t)(m_blk + m) * lda + k0 + k];
-            }
-            if (TB) {
-                const int k = idx & (TK - 1), n = idx >> 5;
-                Bs[k][n] = B[(int64_t)(n_blk + n) * ldb + k0 + k];
-            } else {
-                const int n = idx & (TN - 1), k = idx >> 6;
-                Bs[k][n] = B[(int64_t)(k0 + k) * ldb + n_blk + n];
-            }
-        }
+    u32x4 ga = *reinterpret_cast<const u32x4*>(a_src(k_beg));
+    u32x4 gb = *reinterpret_cast<const u32x4*>(b_src(k_beg));
+    for (int k0 = k_beg; k0 < k_end; k0 += TK) {
+        *reinterpret_cast<u32x4*>(&As[ar][ac]) = ga;
+        *reinterpret_cast<u32x4*>(&Bs[br][bc]) = gb;
         __syncthreads();
+        if (k0 + TK < k_end) {
+            ga = *reinterpret_cast<const u32x4*>(a_src(k0 + TK));
+            gb = *reinterpret_cast<const u32x4*>(b_src(k0 + TK));
+        }
+        if (db_blk) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) db += bf_to_f(Bs[8 * (tid >> 6) + i][tid & 63]);
+        }
         bf16x8 a[2], b[2];
 #pragma unroll
         for (int f = 0; f < 2; ++f) {
+            const int am = wm + f * 16 + (lane & 15), bn = wn + f * 16 + (lane & 15), k8 = 8 * (lane >> 4);
+            if constexpr (TA) {
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                a[f][i] = __builtin_bit_cast(__bf16, As[wm + f * 16 + (lane & 15)][8 * (lane >> 4) + i]);
-                b[f][i] = __builtin_bit_cast(__bf16, Bs[8 * (lane >> 4) + i][wn + f * 16 + (lane & 15)]);
+                for (int i = 0; i < 8; ++i) a[f][i] = __builtin_bit_cast(__bf16, As[k8 + i][am]);
+            } else {
+                a[f] = *reinterpret_cast<const bf16x8*>(&As[am][k8]);
+            }
+            if constexpr (TB) {
+                b[f] = *reinterpret_cast<const bf16x8*>(&Bs[bn][k8]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) b[f][i] = __builtin_bit_cast(__bf16, Bs[k8 + i][bn]);
             }
         }
 #pragma unroll
@@ -96,7 +149,15 @@ __global__ void __launch_bounds__(GEMM_THREADS) gemm_bf16(const uint16_t* __rest
             for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         __syncthreads();
     }
-    float* Cs = C + (int64_t)blockIdx.z * M * ldc;
+    float* Cs = C + (int64_t)blockIdx.z * split_stride;
+    if constexpr (DB) {
+        if (db_blk) { // uniform over the workgroup
+            __shared__ float part[4][64];
+            part[tid >> 6][tid & 63] = db;
+            __syncthreads();
+            if (tid < 64) Cs[(int64_t)M * ldc + n_blk + tid] = ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
+        }
+    }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -105,7 +166,20 @@ __global__ void __launch_bounds__(GEMM_THREADS) gemm_bf16(const uint16_t* __rest
             for (int r = 0; r < 4; ++r) {
                 const int m = m_blk + wm + i * 16 + 4 * (lane >> 4) + r;
                 const int n = n_blk + wn + j * 16 + (lane & 15);
-                Cs[(int64_t)m * ldc + n] = acc[i][j][r];
+                const int64_t t = (int64_t)m * ldc + n;
+                const float v = acc[i][j][r];
+                if constexpr (EPI == EPI_STORE || EPI == EPI_STORE_DB) {
+                    Cs[t] = v;
+                } else if constexpr (EPI == EPI_BIAS_SILU) {
+                    const float z = v + ep.bias[n];
+                    ep.z[t] = z;
+                    ep.act[t] = f_to_bf(z * sigmoid(z));
+                } else if constexpr (EPI == EPI_BIAS_OUT) {
+                    if (n < ep.keep) ep.y[(int64_t)m * ep.keep + n] = v + ep.bias[n];
+                } else {
+                    const float z = ep.z[t], sg = sigmoid(z);
+                    ep.act[t] = f_to_bf(v * sg * (1.0f + z * (1.0f - sg)));
+                }
             }
 }
 
@@ -129,28 +203,6 @@ __global__ void features(const float* __restrict__ p, const float* __restrict__ 
             v = c < 3 + nf ? sinf(arg) : cosf(arg);
         }
         X[t] = f_to_bf(v);
-    }
-}
-
-__device__ __forceinline__ float sigmoid(float z) { return 1.0f / (1.0f + __expf(-z)); }
-
-// Hidden layer epilogue: Z = C + b (kept in FP32 for the backward pass),
-// A = silu(Z) = Z sigmoid(Z) as bf16.  Output layer (act == 0): Y = C + b for
-// the first `keep` columns, written densely [n][keep].
-__global__ void bias_act(const float* __restrict__ Cm, const float* __restrict__ b, int n, int N, int act,
-                         float* __restrict__ Z, uint16_t* __restrict__ A, int keep, float* __restrict__ Y)
-{
-    const int64_t total = (int64_t)n * N;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int c = (int)(t % N);
-        const float z = Cm[t] + b[c];
-        if (act) {
-            Z[t] = z;
-            A[t] = f_to_bf(z * sigmoid(z));
-        } else if (c < keep) {
-            Y[(t / N) * keep + c] = z;
-        }
     }
 }
 
@@ -182,17 +234,6 @@ __global__ void __launch_bounds__(256) mse_grad(const float* __restrict__ Y, con
     if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = acc;
     __syncthreads();
     if (threadIdx.x == 0) partial[blockIdx.x] = ((lds[0] + lds[1]) + lds[2]) + lds[3];
-}
-
-// dZ = dA * silu'(Z), silu'(z) = sigmoid(z) (1 + z (1 - sigmoid(z))); bf16 out.
-__global__ void silu_backward(const float* __restrict__ dA, const float* __restrict__ Z, int64_t total,
-                              uint16_t* __restrict__ dZ)
-{
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const float z = Z[t], sg = sigmoid(z);
-        dZ[t] = f_to_bf(dA[t] * sg * (1.0f + z * (1.0f - sg)));
-    }
 }
 
 // out[c] = sum over r < rows of in[r * ld + c] for c < cols, in row order

@@ -24,6 +24,7 @@ using smrt_host::hip_fail;
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int kReduceRows = 64; // rows summed per chunk in a column-sum pass
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct MlpLayout {
@@ -35,7 +36,7 @@ struct MlpLayout {
     int max_splits = 512;
     // byte offsets in the workspace
     size_t off_params = 0, off_wbf = 0, off_grad = 0, off_m = 0, off_v = 0, off_fourier = 0, off_x0 = 0,
-           off_z = 0, off_a = 0, off_c = 0, off_y = 0, off_dy = 0, off_dz0 = 0, off_dz1 = 0, off_wpart = 0,
+           off_z = 0, off_a = 0, off_y = 0, off_dy = 0, off_dz0 = 0, off_dz1 = 0, off_wpart = 0,
            off_red0 = 0, off_red1 = 0, off_loss = 0, total = 0;
     size_t z_stride = 0, a_stride = 0; // elements between hidden layers' Z / A arrays
     int loss_blocks = 0;
@@ -69,7 +70,7 @@ int make_layout(const smrt_mlp_params* p, MlpLayout* out)
         L.out.push_back(l == L.layers - 1 ? L.n_last : L.width);
         L.out_real.push_back(l == L.layers - 1 ? L.outputs : L.width);
     }
-    size_t pp = 0, rp = 0, max_w = 0;
+    size_t pp = 0, rp = 0, max_w = 0, max_wb = 0;
     for (int l = 0; l < L.layers; ++l) {
         L.w_off.push_back(pp);
         pp += (size_t)L.in[l] * L.out[l];
@@ -77,6 +78,7 @@ int make_layout(const smrt_mlp_params* p, MlpLayout* out)
         pp += L.out[l];
         rp += (size_t)L.in_real[l] * L.out_real[l] + L.out_real[l];
         max_w = std::max(max_w, (size_t)L.in[l] * L.out[l]);
+        max_wb = std::max(max_wb, (size_t)L.in[l] * L.out[l] + L.out[l]);
     }
     L.padded_params = pp;
     L.real_params = rp;
@@ -100,15 +102,15 @@ int make_layout(const smrt_mlp_params* p, MlpLayout* out)
     L.off_x0 = take(mb * L.k0 * 2);
     L.off_z = take((size_t)hidden * L.z_stride * 4);
     L.off_a = take((size_t)hidden * L.a_stride * 2);
-    L.off_c = take(mb * std::max(L.width, L.n_last) * 4);
     L.off_y = take(mb * L.outputs * 4);
     L.off_dy = take(mb * L.n_last * 2);
     L.off_dz0 = take(mb * L.width * 2);
     L.off_dz1 = take(mb * L.width * 2);
-    L.off_wpart = take((size_t)L.max_splits * max_w * 4);
-    // column-sum passes: 16-row chunk sums of the split partials or of dZ
-    const size_t red = std::max((size_t)(L.max_splits + 15) / 16 * max_w,
-                                (mb + 15) / 16 * (size_t)std::max(L.width, L.n_last));
+    // per split: the weight-gradient partial (in x out) and the bias-gradient
+    // partial (out) after it, the layout of a layer's W and b in the parameters
+    L.off_wpart = take((size_t)L.max_splits * max_wb * 4);
+    // column-sum passes: chunk sums of the split partials
+    const size_t red = (size_t)(L.max_splits + kReduceRows - 1) / kReduceRows * max_wb;
     L.off_red0 = take(red * 4);
     L.off_red1 = take(red * 4);
     L.off_loss = take((size_t)L.loss_blocks * 8);
@@ -137,7 +139,6 @@ struct smrt_mlp {
     uint16_t* x0() const { return reinterpret_cast<uint16_t*>(ws + L.off_x0); }
     float* z(int l) const { return reinterpret_cast<float*>(ws + L.off_z) + (size_t)l * L.z_stride; }
     uint16_t* a(int l) const { return reinterpret_cast<uint16_t*>(ws + L.off_a) + (size_t)l * L.a_stride; }
-    float* cbuf() const { return reinterpret_cast<float*>(ws + L.off_c); }
     float* y() const { return reinterpret_cast<float*>(ws + L.off_y); }
     uint16_t* dy() const { return reinterpret_cast<uint16_t*>(ws + L.off_dy); }
     uint16_t* dz(int i) const { return reinterpret_cast<uint16_t*>(ws + (i ? L.off_dz1 : L.off_dz0)); }
@@ -150,18 +151,42 @@ namespace {
 
 int blocks_for(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 65536); }
 
-// C (+ split offset) = opA x opB through the MFMA kernel.
+// C (+ split offset) = opA x opB through the MFMA kernel, or with one split
+// one of the fused epilogues (forward: opA, opB not transposed; input
+// gradient: opB transposed).
 int gemm(hipStream_t s, bool ta, bool tb, const uint16_t* A, const uint16_t* B, float* C, int M, int N, int K,
-         int lda, int ldb, int ldc, int splits)
+         int lda, int ldb, int ldc, int splits, int epi = smrt::mlp::EPI_STORE, smrt::mlp::Epilogue ep = {},
+         int64_t split_stride = -1)
 {
+    if (split_stride < 0) split_stride = (int64_t)M * ldc;
     if (M % smrt::mlp::TM || N % smrt::mlp::TN || K % (smrt::mlp::TK * splits))
         return fail(SMRT_EINVAL, "gemm shape %d x %d x %d (splits %d) not tile-aligned", M, N, K, splits);
+    // operand slices are staged 8 elements (16 bytes) at a time
+    if (lda % 8 || ldb % 8 || reinterpret_cast<uintptr_t>(A) % 16 || reinterpret_cast<uintptr_t>(B) % 16)
+        return fail(SMRT_EINVAL, "gemm operands need 16-byte alignment and leading dimensions that are multiples of 8 "
+                                 "(lda %d, ldb %d)", lda, ldb);
     dim3 grid(N / smrt::mlp::TN, M / smrt::mlp::TM, splits);
     const int ks = K / splits;
-    if (!ta && !tb) smrt::mlp::gemm_bf16<false, false><<<grid, smrt::mlp::GEMM_THREADS, 0, s>>>(A, B, C, M, N, lda, ldb, ldc, ks);
-    else if (ta && !tb) smrt::mlp::gemm_bf16<true, false><<<grid, smrt::mlp::GEMM_THREADS, 0, s>>>(A, B, C, M, N, lda, ldb, ldc, ks);
-    else if (!ta && tb) smrt::mlp::gemm_bf16<false, true><<<grid, smrt::mlp::GEMM_THREADS, 0, s>>>(A, B, C, M, N, lda, ldb, ldc, ks);
-    else smrt::mlp::gemm_bf16<true, true><<<grid, smrt::mlp::GEMM_THREADS, 0, s>>>(A, B, C, M, N, lda, ldb, ldc, ks);
+    using namespace smrt::mlp;
+    constexpr int T = GEMM_THREADS;
+    const int64_t ss = split_stride;
+    if (epi == EPI_STORE_DB) {
+        if (!ta || tb) return fail(SMRT_EINVAL, "bias-gradient sums need opA transposed and opB not");
+        gemm_bf16<true, false, EPI_STORE_DB><<<grid, T, 0, s>>>(A, B, C, M, N, lda, ldb, ldc, ks, ss, ep);
+        return after_launch("gemm_bf16");
+    }
+    if (epi != EPI_STORE) {
+        if (splits != 1 || ta || tb != (epi == EPI_SILU_GRAD))
+            return fail(SMRT_EINVAL, "fused epilogue %d needs one split and its own transposition", epi);
+        if (epi == EPI_BIAS_SILU) gemm_bf16<false, false, EPI_BIAS_SILU><<<grid, T, 0, s>>>(A, B, C, M, N, lda, ldb, ldc, ks, ss, ep);
+        else if (epi == EPI_BIAS_OUT) gemm_bf16<false, false, EPI_BIAS_OUT><<<grid, T, 0, s>>>(A, B, C, M, N, lda, ldb, ldc, ks, ss, ep);
+        else gemm_bf16<false, true, EPI_SILU_GRAD><<<grid, T, 0, s>>>(A, B, C, M, N, lda, ldb, ldc, ks, ss, ep);
+        return after_launch("gemm_bf16");
+    }
+    if (!ta && !tb) gemm_bf16<false, false><<<grid, T, 0, s>>>(A, B, C, M, N, lda, ldb, ldc, ks, ss, ep);
+    else if (ta && !tb) gemm_bf16<true, false><<<grid, T, 0, s>>>(A, B, C, M, N, lda, ldb, ldc, ks, ss, ep);
+    else if (!ta && tb) gemm_bf16<false, true><<<grid, T, 0, s>>>(A, B, C, M, N, lda, ldb, ldc, ks, ss, ep);
+    else gemm_bf16<true, true><<<grid, T, 0, s>>>(A, B, C, M, N, lda, ldb, ldc, ks, ss, ep);
     return after_launch("gemm_bf16");
 }
 
@@ -184,16 +209,19 @@ int forward(smrt_mlp* m, const float* pts, int n, float* out)
     for (int l = 0; l < L.layers; ++l) {
         const uint16_t* in = l == 0 ? m->x0() : m->a(l - 1);
         const int K = L.in[l], N = L.out[l];
-        rc = gemm(s, false, false, in, m->wbf() + L.w_off[l], m->cbuf(), n, N, K, K, N, N, 1);
-        if (rc) return rc;
-        const float* b = m->params() + L.b_off[l];
-        if (l < L.layers - 1)
-            smrt::mlp::bias_act<<<blocks_for((int64_t)n * N), 256, 0, s>>>(m->cbuf(), b, n, N, 1, m->z(l), m->a(l), 0,
-                                                                          nullptr);
-        else
-            smrt::mlp::bias_act<<<blocks_for((int64_t)n * N), 256, 0, s>>>(m->cbuf(), b, n, N, 0, nullptr, nullptr,
-                                                                          L.outputs, out);
-        rc = after_launch("bias_act");
+        // Z = in W + b with the bias and the activation in the product's epilogue
+        smrt::mlp::Epilogue ep;
+        ep.bias = m->params() + L.b_off[l];
+        const bool hidden = l < L.layers - 1;
+        if (hidden) {
+            ep.z = m->z(l);
+            ep.act = m->a(l);
+        } else {
+            ep.y = out;
+            ep.keep = L.outputs;
+        }
+        rc = gemm(s, false, false, in, m->wbf() + L.w_off[l], nullptr, n, N, K, K, N, N, 1,
+                  hidden ? smrt::mlp::EPI_BIAS_SILU : smrt::mlp::EPI_BIAS_OUT, ep);
         if (rc) return rc;
     }
     return SMRT_OK;
@@ -210,13 +238,13 @@ int splits_for(int n)
 }
 
 // Column sums of a rows x cols array (row stride ld) into out[cols], in a
-// fixed order: passes of 16-row chunk sums (the first pass with longer
-// chunks when rows / 16 would exceed the grid) until at most 16 rows remain,
-// then one pass of plain sums.
+// fixed order: passes of kReduceRows-row chunk sums (the first pass with
+// longer chunks when the chunk count would exceed the grid) until at most
+// kReduceRows rows remain, then one pass of plain sums.
 template <typename T>
 void reduce_columns(smrt_mlp* m, hipStream_t s, const T* in, int rows, int cols, int64_t ld, float* out)
 {
-    constexpr int R = 16;
+    constexpr int R = kReduceRows;
     const int bx = (cols + 255) / 256;
     if (rows <= R) {
         smrt::mlp::column_sums<T><<<bx, 256, 0, s>>>(in, rows, cols, ld, out);
@@ -255,23 +283,25 @@ int backward(smrt_mlp* m, const float* target, int n, double* loss)
     for (int l = L.layers - 1; l >= 0; --l) {
         const uint16_t* in = l == 0 ? m->x0() : m->a(l - 1);
         const int K = L.in[l], N = L.out[l];
-        // dW_l = in^T dZ_l, split over the rows, then summed in split order
-        rc = gemm(s, true, false, in, dcur, m->wpart(), K, N, n, K, N, N, splits);
+        // dW_l = in^T dZ_l and db_l = column sums of dZ_l, split over the rows
+        // (the bias partial beside each split's weight partial), then summed
+        // in split order into the layer's contiguous W, b gradient
+        const int64_t wb = (int64_t)K * N + N;
+        rc = gemm(s, true, false, in, dcur, m->wpart(), K, N, n, K, N, N, splits, smrt::mlp::EPI_STORE_DB, {}, wb);
         if (rc) return rc;
-        reduce_columns<float>(m, s, m->wpart(), splits, K * N, (int64_t)K * N, m->grad() + L.w_off[l]);
-        // db_l = column sums of dZ_l
-        reduce_columns<uint16_t>(m, s, dcur, n, N, N, m->grad() + L.b_off[l]);
+        reduce_columns<float>(m, s, m->wpart(), splits, (int)wb, wb, m->grad() + L.w_off[l]);
         rc = after_launch("weight gradients");
         if (rc) return rc;
         if (l == 0) break;
-        // dA_{l-1} = dZ_l W_l^T, then dZ_{l-1} = dA_{l-1} silu'(Z_{l-1})
-        rc = gemm(s, false, true, dcur, m->wbf() + L.w_off[l], m->cbuf(), n, K, N, N, N, K, 1);
-        if (rc) return rc;
+        // dZ_{l-1} = (dZ_l W_l^T) silu'(Z_{l-1}), the activation's derivative in
+        // the product's epilogue
         uint16_t* dnext = m->dz(flip);
         flip ^= 1;
-        smrt::mlp::silu_backward<<<blocks_for((int64_t)n * K), 256, 0, s>>>(m->cbuf(), m->z(l - 1), (int64_t)n * K,
-                                                                            dnext);
-        rc = after_launch("silu_backward");
+        smrt::mlp::Epilogue ep;
+        ep.z = m->z(l - 1);
+        ep.act = dnext;
+        rc = gemm(s, false, true, dcur, m->wbf() + L.w_off[l], nullptr, n, K, N, N, N, K, 1,
+                  smrt::mlp::EPI_SILU_GRAD, ep);
         if (rc) return rc;
         dcur = dnext;
     }

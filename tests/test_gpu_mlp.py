@@ -112,6 +112,8 @@ def test_gemm_bf16_rejects_unaligned(smrt):
         smrt.gemm_bf16(z, z, 64, 64, 48, 64, 64, 64)      # K not a multiple of 32
     with pytest.raises(smrt.SmrtError):
         smrt.gemm_bf16(z, z, 32, 64, 32, 64, 64, 64)      # M not a multiple of 64
+    with pytest.raises(smrt.SmrtError):
+        smrt.gemm_bf16(z, z, 64, 64, 32, 68, 64, 64)      # lda not a multiple of 8
 
 
 def test_training_reduces_loss(smrt):
