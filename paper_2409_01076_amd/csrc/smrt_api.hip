@@ -496,7 +496,8 @@ int smrt_create(const smrt_params* p, void* dev_ws, size_t ws_bytes, smrt_ctx** 
         // Default block shape: one row segment per block, as wide as the
         // lattice allows (512 measured best on 4096^2, within 1-2% of 256).
         // FP32 and 16-bit storage take the LDS-blocked kernels, tiles in XCD
-        // panels of 16 tile columns, 512 threads per workgroup.  Measured on
+        // panels of 16 tile columns (threads per workgroup by tile and step
+        // count: multi_threads).  Measured on
         // 512^2 .. 4096^2: FP32 storage five steps per launch, with 64 x 22
         // tiles while that gives >= 1024 workgroups, else 64 x 16 while that
         // gives >= 256; 16-bit storage four steps, with 64 x 26 tiles while
@@ -709,7 +710,7 @@ double smrt_tau(const smrt_ctx* c) { return c ? c->tau : std::numeric_limits<dou
 int smrt_set_launch(smrt_ctx* c, int32_t bx, int32_t by, int32_t rows)
 {
     if (!c) return fail(SMRT_EINVAL, "context is NULL");
-    const int threads = bx * by;
+    const int64_t threads = (int64_t)bx * by;
     if (bx < 16 || bx % 16 || by < 1 || (threads != 64 && threads != 128 && threads != 256 && threads != 512 &&
                                           threads != 1024))
         return fail(SMRT_EINVAL, "invalid block shape %d x %d", bx, by);
