@@ -212,17 +212,19 @@ int upload_tables(smrt_batch* b)
         b->table_order.push_back(i);
     }
     b->ntiles = (int)table.size();
-    HIP_TRY(hipMemcpyAsync(b->desc(), desc.data(), desc.size() * sizeof(smrt::CavityDesc), hipMemcpyHostToDevice,
-                           b->stream));
-    if (!table.empty()) {
-        HIP_TRY(hipMemcpyAsync(b->table(), table.data(), table.size() * sizeof(int2), hipMemcpyHostToDevice,
-                               b->stream));
-        HIP_TRY(hipMemcpyAsync(b->ranges(), ranges.data(), ranges.size() * sizeof(int2), hipMemcpyHostToDevice,
-                               b->stream));
-    }
-    int n = b->ntiles;
-    HIP_TRY(hipMemcpyAsync(b->ntiles_dev(), &n, sizeof(int), hipMemcpyHostToDevice, b->stream));
-    HIP_TRY(hipStreamSynchronize(b->stream));
+    const int n = b->ntiles;
+    // The copies read these local buffers: wait for them even when one fails.
+    hipError_t e = hipMemcpyAsync(b->desc(), desc.data(), desc.size() * sizeof(smrt::CavityDesc),
+                                  hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess && !table.empty())
+        e = hipMemcpyAsync(b->table(), table.data(), table.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess && !table.empty())
+        e = hipMemcpyAsync(b->ranges(), ranges.data(), ranges.size() * sizeof(int2), hipMemcpyHostToDevice,
+                           b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->ntiles_dev(), &n, sizeof(int), hipMemcpyHostToDevice, b->stream);
+    const hipError_t w = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(e, "upload_tables: hipMemcpyAsync");
+    if (w != hipSuccess) return hip_fail(w, "upload_tables: hipStreamSynchronize");
     return SMRT_OK;
 }
 
@@ -263,12 +265,16 @@ void launch_five_tile(smrt_batch* b, hipStream_t s, int parity, dim3 grid)
         b->desc(), b->table(), b->ntiles_dev(), reinterpret_cast<T*>(b->state()), parity);
 }
 
-// One launch of k time steps (k = 2 .. 5: 64 x shape.by tiles; the tile
-// table is built for that shape, so a shorter remainder launch uses the same
-// table).
-template <typename T, int SCHEME> void launch_typed_scheme(smrt_batch* b, hipStream_t s, int parity, int k)
+template <typename T, int SCHEME> void launch_one(smrt_batch* b, hipStream_t s, int parity, dim3 grid)
 {
-    dim3 grid((unsigned)std::max(b->grid, 1));
+    dim3 block(b->shape.bx, b->shape.by);
+    smrt::batch_stream_collide<T, SCHEME><<<grid, block, 0, s>>>(b->desc(), b->table(), b->ntiles_dev(),
+                                                                reinterpret_cast<T*>(b->state()), parity, b->shape);
+}
+
+template <typename T, int SCHEME>
+void launch_multi_or_one(smrt_batch* b, hipStream_t s, int parity, int k, dim3 grid)
+{
     if (k == 5) {
         if (b->shape.by == 16) launch_five_tile<T, SCHEME, 16>(b, s, parity, grid);
         else launch_five_tile<T, SCHEME, 8>(b, s, parity, grid);
@@ -290,9 +296,18 @@ template <typename T, int SCHEME> void launch_typed_scheme(smrt_batch* b, hipStr
         else launch_two_tile<T, SCHEME, 4>(b, s, parity, grid);
         return;
     }
-    dim3 block(b->shape.bx, b->shape.by);
-    smrt::batch_stream_collide<T, SCHEME><<<grid, block, 0, s>>>(b->desc(), b->table(), b->ntiles_dev(),
-                                                                reinterpret_cast<T*>(b->state()), parity, b->shape);
+    launch_one<T, SCHEME>(b, s, parity, grid);
+}
+
+// One launch of k time steps (k = 2 .. 5: 64 x shape.by tiles; the tile
+// table is built for that shape, so a shorter remainder launch uses the same
+// table).  FP64 batches take one step per launch (multi_steps), so their
+// multi-step kernels are not built.
+template <typename T, int SCHEME> void launch_typed_scheme(smrt_batch* b, hipStream_t s, int parity, int k)
+{
+    dim3 grid((unsigned)std::max(b->grid, 1));
+    if constexpr (!std::is_same_v<T, double>) launch_multi_or_one<T, SCHEME>(b, s, parity, k, grid);
+    else launch_one<T, SCHEME>(b, s, parity, grid);
 }
 
 template <typename T> void launch_step_typed(smrt_batch* b, hipStream_t s, int parity, int k)
@@ -588,9 +603,18 @@ int smrt_batch_autotune(smrt_batch* b, int32_t steps, int32_t* chosen)
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
             cus = prop.multiProcessorCount;
     }
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
+    // timing events, destroyed on every return
+    struct Events {
+        hipEvent_t e[2] = {nullptr, nullptr};
+        ~Events()
+        {
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } ev;
+    HIP_TRY(hipEventCreate(&ev.e[0]));
+    HIP_TRY(hipEventCreate(&ev.e[1]));
+    hipEvent_t e0 = ev.e[0], e1 = ev.e[1];
     float best = std::numeric_limits<float>::infinity();
     smrt::BatchLaunch best_shape = b->shape;
     int best_grid = b->grid;
@@ -637,8 +661,6 @@ int smrt_batch_autotune(smrt_batch* b, int32_t steps, int32_t* chosen)
             }
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (rc) return rc;
     b->shape = best_shape;
     b->multi = best_multi;
