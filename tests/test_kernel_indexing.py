@@ -19,7 +19,8 @@ way the kernels index, on lattices from 3 x 3 up with ragged tiles, and checks:
 * the XCD panel tile order visits every tile exactly once.
 
 Launch shapes and thread counts mirror smrt_set_steps_per_launch and
-multi_threads in smrt_api.hip.
+multi_threads in smrt_api.hip, and the batch shapes and per-cavity layout of
+smrt_batch.hip.
 """
 import itertools
 
@@ -32,10 +33,12 @@ OPP = np.array([0, 3, 4, 1, 2, 7, 8, 5, 6])
 U32 = (1 << 32) - 1
 
 
-def layout(nx, ny, e):
-    """(pitch, plane) in elements."""
+def layout(nx, ny, e, batch=False):
+    """(pitch, plane) in elements; a batch packs each cavity's planes tighter."""
     per_row = 256 // e
     pitch = -(-nx // per_row) * per_row
+    if batch:
+        return pitch, -(-pitch * ny // per_row) * per_row
     plane_bytes = -(-pitch * ny * e // 65536) * 65536 + 4096
     return pitch, plane_bytes // e
 
@@ -53,9 +56,9 @@ TILES_64 = [(2, 64, 4), (2, 64, 8), (3, 64, 8), (4, 64, 8), (4, 64, 10)]
 
 
 class Buffer:
-    def __init__(self, nx, ny, e):
+    def __init__(self, nx, ny, e, batch=False):
         self.nx, self.ny, self.e = nx, ny, e
-        self.pitch, self.plane = layout(nx, ny, e)
+        self.pitch, self.plane = layout(nx, ny, e, batch)
         self.limit = 9 * self.plane * e
 
     def check(self, addr, what):
@@ -96,9 +99,10 @@ class Buffer:
         self.check(self.pull_interior(row0, x[~edge], y[~edge]), "interior pull")
 
 
-def one_step(nx, ny, e, periodic, bx, by, rows):
-    """stream_collide: block (bx, by), each thread `rows` nodes by rows apart."""
-    buf = Buffer(nx, ny, e)
+def one_step(nx, ny, e, periodic, bx, by, rows, batch=False):
+    """stream_collide: block (bx, by), each thread `rows` nodes by rows apart
+    (batch_stream_collide: rows = 1, per cavity)."""
+    buf = Buffer(nx, ny, e, batch)
     tiles_x, tiles_y = -(-nx // bx), -(-ny // (by * rows))
     tix, tiy = (a.ravel() for a in np.meshgrid(np.arange(bx), np.arange(by)))
     for ty, tx in itertools.product(range(tiles_y), range(tiles_x)):
@@ -111,9 +115,10 @@ def one_step(nx, ny, e, periodic, bx, by, rows):
             buf.check(buf.store(ytile, x[m], y[m]), "store")
 
 
-def multi_step(nx, ny, e, periodic, S, TX, TY):
-    """stream_collide_xS on every TX x TY tile: HBM phase, LDS frame, store."""
-    buf = Buffer(nx, ny, e)
+def multi_step(nx, ny, e, periodic, S, TX, TY, batch=False):
+    """stream_collide_xS (batch_stream_collide_xS: per cavity) on every
+    TX x TY tile: HBM phase, LDS frame, store."""
+    buf = Buffer(nx, ny, e, batch)
     NT = threads(S, TX, TY)
     R = S - 1
     FX, FY = TX + 2 * R, TY + 2 * R
@@ -204,6 +209,25 @@ def test_multi_step_kernels_fp32_and_16bit(S, TX, TY):
 def test_multi_step_kernels_fp64(S, TX, TY):
     for S_, TX_, TY_, nx, ny, periodic in multi_cases([(S, TX, TY)]):
         multi_step(nx, ny, 8, periodic, S_, TX_, TY_)
+
+
+# batch launch shapes (smrt_batch.hip): one-step blocks, multi-step tiles (no FP64)
+BATCH_BLOCKS = [(64, 4), (128, 2), (256, 1), (32, 8), (64, 8), (128, 4), (256, 2), (512, 1)]
+BATCH_TILES = [(2, 64, 4), (2, 64, 8), (2, 64, 16), (3, 64, 8), (3, 64, 16), (4, 64, 8), (4, 64, 16), (5, 64, 16)]
+BATCH_SIZES = [3, 17, 64, 65, 100, 157, 300]
+
+
+@pytest.mark.parametrize("e", [8, 4, 2])
+def test_batch_kernels_stay_in_their_cavity(e):
+    # an address past a cavity's own planes lands in the next cavity: no
+    # fault, silent corruption, so each cavity is checked against its region
+    for nx, ny in itertools.product(BATCH_SIZES, BATCH_SIZES):
+        for bx, by in BATCH_BLOCKS:
+            one_step(nx, ny, e, False, bx, by, 1, batch=True)
+        if e == 8:
+            continue
+        for S, TX, TY in BATCH_TILES:
+            multi_step(nx, ny, e, False, S, TX, TY, batch=True)
 
 
 def test_replay_catches_a_negative_row_offset():
