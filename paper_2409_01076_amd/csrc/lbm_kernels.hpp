@@ -201,9 +201,17 @@ template <typename C> struct Coef {
 //   q_0 = drho - 2 (s_x + s_y + s_5 + s_6)                      (w_0 (...)).
 //
 // 1/rho enters only the terms quadratic in u, so FP32 takes the hardware
-// reciprocal (1 ulp) instead of a correctly rounded division; FP64 divides.
+// reciprocal (1 ulp) instead of a correctly rounded division.  FP64 refines
+// the hardware reciprocal with two Newton steps, r <- r + r (1 - x r), each of
+// which squares the relative error: about one ulp, in 5 instructions where a
+// correctly rounded division takes 11.
 __device__ __forceinline__ float reciprocal(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double reciprocal(double x) { return 1.0 / x; }
+__device__ __forceinline__ double reciprocal(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+    return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+}
 
 template <int SCHEME, typename T, typename C = typename Storage<T>::C>
 __device__ __forceinline__ void collide(C d[9], const Coef<C>& k)
