@@ -188,7 +188,7 @@ int smrt_set_steps_per_launch(smrt_ctx* c, int32_t steps, int32_t tile_cols, int
 /* Time steps per launch in use (1 .. 5); -1 for c == NULL. */
 int32_t smrt_get_steps_per_launch(const smrt_ctx* c);
 
-/* Order in which the two-step kernel's workgroups take their tiles (a
+/* Order in which the multi-step kernels' workgroups take their tiles (a
  * performance knob only: every order computes bitwise the same result).
  * panel_cols = 0: row-major.  panel_cols = P > 0: the tile columns are cut
  * into panels of P, each walked top to bottom, and each of the GPU's 8 XCDs

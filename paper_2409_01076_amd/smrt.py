@@ -369,8 +369,8 @@ class Solver:
         _check(load().smrt_set_steps_per_launch(self._ctx, int(steps), int(tile_cols), int(tile_rows)))
 
     def set_tile_order(self, panel_cols):
-        """Two-step tile order: 0 = row-major, P > 0 = XCD panels of P tile
-        columns (same results, different L2 reuse)."""
+        """Tile order of the multi-step kernels: 0 = row-major, P > 0 = XCD
+        panels of P tile columns (same results, different L2 reuse)."""
         _check(load().smrt_set_tile_order(self._ctx, int(panel_cols)))
 
     def synchronize(self):
