@@ -194,8 +194,8 @@ int32_t smrt_get_steps_per_launch(const smrt_ctx* c);
  * into panels of P, each walked top to bottom, and each of the GPU's 8 XCDs
  * takes one contiguous run of that order, so neighbouring tiles share an L2
  * and the halo rows and columns they both read are fetched from memory once.
- * Default at creation: 16, or 32 (one panel) for lattices of at most 32
- * tile columns of 64 nodes (FP64 storage: 32).  SMRT_EINVAL for
+ * Default at creation: 16, or one panel for lattices of at most 48 tile
+ * columns of 64 nodes (FP64 storage: 32).  SMRT_EINVAL for
  * c == NULL or panel_cols < 0. */
 int smrt_set_tile_order(smrt_ctx* c, int32_t panel_cols);
 

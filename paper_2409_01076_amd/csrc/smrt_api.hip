@@ -496,7 +496,7 @@ int smrt_create(const smrt_params* p, void* dev_ws, size_t ws_bytes, smrt_ctx** 
         // Default block shape: one row segment per block, as wide as the
         // lattice allows (512 measured best on 4096^2, within 1-2% of 256).
         // FP32 and 16-bit storage take the LDS-blocked kernels, tiles in XCD
-        // panels of 16 tile columns, or one panel up to 32 (threads per
+        // panels of 16 tile columns, or one panel up to 48 (threads per
         // workgroup by tile and step count: multi_threads).  Measured on
         // 512^2 .. 4096^2: FP32 storage five steps per launch, with 64 x 22
         // tiles while that gives >= 1024 workgroups, else 64 x 16 while that
@@ -523,10 +523,12 @@ int smrt_create(const smrt_params* p, void* dev_ws, size_t ws_bytes, smrt_ctx** 
                 return !per || (p->nx >= 64 + 2 * (steps - 1) && p->ny >= rows + 2 * (steps - 1));
             };
             c->fused_cols = 64;
-            // one XCD panel across the whole lattice up to 32 tile columns
-            // (2048^2 cavity, five steps: 245.8 GLUPS against 229.8 with
-            // panels of 16), panels of 16 beyond (4096^2: 270.0 against 268.0)
-            c->panel = cols <= 32 ? 32 : 16;
+            // one XCD panel across the whole lattice up to 48 tile columns
+            // (five steps: 2048^2 cavity 245.8 GLUPS against 229.8 with panels
+            // of 16, 3072^2 274.5 against 268.2), where one row of tiles'
+            // rings (~78 KB each) still fits an XCD's 4 MB L2 for the row
+            // below; panels of 16 beyond (4096^2: 269.6 against 267.4)
+            c->panel = cols <= 48 ? 48 : 16;
             const int deep = p->storage == SMRT_F32 ? 5 : 4, tall = p->storage == SMRT_F32 ? 22 : 26;
             if (tiles(tall) >= 1024 && fits(deep, tall)) {
                 c->fused = deep;
