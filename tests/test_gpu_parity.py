@@ -387,11 +387,12 @@ def test_two_step_kernel_small_cavities(smrt, nx, ny):
 @pytest.mark.parametrize("tile", [(64, 8), (64, 16), (128, 4)])
 def test_tile_order_does_not_change_results(smrt, boundary, tile):
     """Every tile order (row-major, XCD panels of several widths, ragged last
-    panel, a panel wider than the lattice) computes each tile exactly once."""
+    panel, a panel wider than the lattice, one whose product with the tile
+    rows would overflow 32 bits) computes each tile exactly once."""
     nx, ny, steps = 203, 77, 20
     f0 = inputs.perturbed_populations(nx, ny, eps=0.03, seed=6)
     outs = []
-    for panel in (0, 1, 3, 8, 1000):
+    for panel in (0, 1, 3, 8, 1000, 2**31 - 1):  # the widest is clamped to the tile columns
         with smrt.Solver(nx, ny, scheme="smrt", boundary=boundary, storage="f32", tau=0.56,
                          u_lid=0.1 if boundary == "cavity" else 0.0) as s:
             s.set_populations(to_dev(f0, torch.float64))
@@ -495,7 +496,7 @@ def test_multi_step_tile_order_does_not_change_results(smrt, boundary, multi):
     nx, ny, steps = 203, 77, 21
     f0 = inputs.perturbed_populations(nx, ny, eps=0.03, seed=8)
     outs = []
-    for panel in (0, 1, 3, 8, 1000):
+    for panel in (0, 1, 3, 8, 1000, 2**31 - 1):  # the widest is clamped to the tile columns
         with smrt.Solver(nx, ny, scheme="smrt", boundary=boundary, storage="f32", tau=0.56,
                          u_lid=0.1 if boundary == "cavity" else 0.0) as s:
             s.set_populations(to_dev(f0, torch.float64))
