@@ -175,7 +175,8 @@ int smrt_set_launch(smrt_ctx* c, int32_t bx, int32_t by, int32_t rows);
  * ny >= tile_rows + 2r with r = steps - 1.  Per node the arithmetic is
  * unchanged: results are bitwise those of single-step launches.  Default at
  * creation: FP32 storage 5 steps with a 64 x 22 tile while that gives >= 1024
- * tiles, else with 64 x 16 while that gives >= 256; 16-bit storage 4 steps
+ * tiles or while 64 x 16 tiles would need between one and two waves of two
+ * workgroups per CU, else with 64 x 16 while that gives >= 256; 16-bit storage 4 steps
  * with a 64 x 26 tile while that gives >= 1024 tiles, else with 64 x 16
  * while that gives >= 256; smaller lattices 2 steps with a 64 x 32 tile
  * while that gives >= 512 tiles, else with 64 x 4; FP64 storage 4 steps with

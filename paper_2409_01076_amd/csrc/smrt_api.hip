@@ -499,7 +499,8 @@ int smrt_create(const smrt_params* p, void* dev_ws, size_t ws_bytes, smrt_ctx** 
         // panels of 16 tile columns, or one panel up to 48 (threads per
         // workgroup by tile and step count: multi_threads).  Measured on
         // 512^2 .. 4096^2: FP32 storage five steps per launch, with 64 x 22
-        // tiles while that gives >= 1024 workgroups, else 64 x 16 while that
+        // tiles while that gives >= 1024 workgroups or while 64 x 16 tiles
+        // would leave a short second wave (below), else 64 x 16 while that
         // gives >= 256; 16-bit storage four steps, with 64 x 26 tiles while
         // that gives >= 1024 workgroups (the tall tile leaves fewer idle
         // lanes on the rings), else 64 x 16 while that gives >= 256; smaller
@@ -530,7 +531,20 @@ int smrt_create(const smrt_params* p, void* dev_ws, size_t ws_bytes, smrt_ctx** 
             // below; panels of 16 beyond (4096^2: 269.6 against 267.4)
             c->panel = cols <= 48 ? 48 : 16;
             const int deep = p->storage == SMRT_F32 ? 5 : 4, tall = p->storage == SMRT_F32 ? 22 : 26;
-            if (tiles(tall) >= 1024 && fits(deep, tall)) {
+            // Two 768-thread workgroups are resident per CU (LDS), so a launch
+            // runs in waves of 2 x CUs workgroups.  Where 64 x 16 tiles need
+            // more than one wave but less than two, FP32's taller tiles avoid a
+            // short second wave (five steps: 768^2 cavity 154.7 GLUPS against
+            // 140.1, 832^2 177.2 / 153.6, 960^2 171.1 / 165.9; at 1024^2, two
+            // full waves, 64 x 16 stays ahead, 175.5 / 172.3).  16-bit storage
+            // keeps 64 x 16 there (64 x 26 tiles: 768^2 +3 %, 960^2 -4 %).
+            int cus = 256, dev = 0;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+                cus = 256;
+            const int64_t wave = 2 * (int64_t)cus;
+            const bool short_second_wave = p->storage == SMRT_F32 && tiles(16) > wave && tiles(16) < 2 * wave;
+            if ((tiles(tall) >= 1024 || short_second_wave) && fits(deep, tall)) {
                 c->fused = deep;
                 c->fused_rows = tall;
             } else if (tiles(16) >= 256 && fits(deep, 16)) {
