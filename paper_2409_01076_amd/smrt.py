@@ -202,7 +202,9 @@ class Solver:
     current torch stream of that device at construction time.  Calls that take
     or return tensors are ordered against the caller's current stream, so the
     two streams may differ (e.g. a solver created on a side stream for graph
-    capture).
+    capture).  The library launches on the current HIP device: with several
+    devices, create and call a solver with its own device current
+    (``torch.cuda.device``).
     """
 
     def __init__(self, nx, ny, scheme="smrt", boundary="cavity", storage="f32", tau=None,
