@@ -537,13 +537,15 @@ int smrt_create(const smrt_params* p, void* dev_ws, size_t ws_bytes, smrt_ctx** 
             // short second wave (five steps: 768^2 cavity 154.7 GLUPS against
             // 140.1, 832^2 177.2 / 153.6, 960^2 171.1 / 165.9; at 1024^2, two
             // full waves, 64 x 16 stays ahead, 175.5 / 172.3).  16-bit storage
-            // keeps 64 x 16 there (64 x 26 tiles: 768^2 +3 %, 960^2 -4 %).
+            // does so only while its 64 x 26 tiles fit one wave (768^2 +3 %,
+            // 832^2 +5 %; 960^2, 555 tiles, -4 %).
             int cus = 256, dev = 0;
             if (hipGetDevice(&dev) != hipSuccess ||
                 hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
                 cus = 256;
             const int64_t wave = 2 * (int64_t)cus;
-            const bool short_second_wave = p->storage == SMRT_F32 && tiles(16) > wave && tiles(16) < 2 * wave;
+            const bool short_second_wave = tiles(16) > wave && tiles(16) < 2 * wave &&
+                                           (p->storage == SMRT_F32 || tiles(tall) <= wave);
             if ((tiles(tall) >= 1024 || short_second_wave) && fits(deep, tall)) {
                 c->fused = deep;
                 c->fused_rows = tall;
