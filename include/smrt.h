@@ -179,7 +179,8 @@ int smrt_set_launch(smrt_ctx* c, int32_t bx, int32_t by, int32_t rows);
  * workgroups per CU, else with 64 x 16 while that gives >= 256; 16-bit storage 4 steps
  * with a 64 x 26 tile while that gives >= 1024 tiles or (as for FP32) avoids
  * a short second wave with its tiles in one wave, else with 64 x 16
- * while that gives >= 256; smaller lattices 2 steps with a 64 x 32 tile
+ * while that gives >= 256; smaller lattices 4 steps with 64 x 8 tiles;
+ * periodic lattices too small for those rings 2 steps with a 64 x 32 tile
  * while that gives >= 512 tiles, else with 64 x 4; FP64 storage 4 steps with
  * 64 x 10 tiles; lattices too small for the rings: 1.  A step count that is
  * not a multiple ends with one shorter launch (64 x 16 tiles, or 64 x 8 after

@@ -504,9 +504,9 @@ int smrt_create(const smrt_params* p, void* dev_ws, size_t ws_bytes, smrt_ctx** 
         // gives >= 256; 16-bit storage four steps, with 64 x 26 tiles while
         // that gives >= 1024 workgroups (the tall tile leaves fewer idle
         // lanes on the rings), else 64 x 16 while that gives >= 256; smaller
-        // lattices two steps with 64 x 32 tiles while that gives >= 512
-        // workgroups, else with 64 x 4.  Periodic lattices need room for the
-        // rings.
+        // lattices four steps with 64 x 8 tiles; periodic lattices too small
+        // for those rings two steps with 64 x 32 tiles while that gives >= 512
+        // workgroups, else with 64 x 4.
         if (p->storage == SMRT_F64) {
             // FP64 (twice the LDS per node): four steps with 64 x 10 tiles
             // (80.6 KB of LDS, two workgroups per CU), measured best on
@@ -552,6 +552,13 @@ int smrt_create(const smrt_params* p, void* dev_ws, size_t ws_bytes, smrt_ctx** 
             } else if (tiles(16) >= 256 && fits(deep, 16)) {
                 c->fused = deep;
                 c->fused_rows = 16;
+            } else if (fits(4, 8)) {
+                // Small lattices are bound by launch latency and fill few CUs:
+                // four steps on 64 x 8 tiles (768 threads) beat two steps per
+                // launch by 36 .. 52 % on FP32 cavities of 128^2 .. 448^2
+                // (256^2: 37.4 GLUPS against 26.7; 448^2: 86.0 against 59.1).
+                c->fused = 4;
+                c->fused_rows = 8;
             } else {
                 c->fused_rows = tiles(32) >= 512 ? 32 : 4;
                 if (per && p->ny < c->fused_rows + 2) c->fused_rows = 4;
