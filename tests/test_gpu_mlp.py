@@ -1,6 +1,8 @@
 """The warm-start network's GPU kernels: the bf16 MFMA product against an FP64
-product of the same bf16 values, the forward pass and the gradients against the
-FP64 CPU reference (oracle/mlp_oracle.py), and training that reduces the loss."""
+product of the same bf16 values; the forward pass and every gradient entry
+element by element against the bfloat16/binary32 model of the network in the
+CPU oracle (oracle/mlp_oracle.py), each within its own tolerance; and training
+that reduces the loss."""
 import ctypes
 
 import numpy as np
@@ -34,38 +36,54 @@ def make_net(rng, fourier=16, width=128, layers=5, outputs=3):
     return dims, np.concatenate(params), rng.normal(0, 2.0, size=(fourier, 3))
 
 
+# Longest chain of binary32 additions in the library's sums over rows (weight
+# and bias gradients): at most 128 rows per split on the matrix cores, then
+# at most two fixed-order passes over at most 64 partial sums each.
+GRADIENT_DEPTH = 128 + 64 + 64
+
+
 def test_forward_matches_oracle(smrt):
+    """Every output element within its tolerance of the bfloat16/binary32
+    model of the network (oracle/mlp_oracle.py forward_tolerance)."""
     rng = np.random.default_rng(1)
     dims, params, B = make_net(rng)
-    pts = rng.uniform(0, 1, size=(512, 3))
+    params, B = params.astype(np.float32), B.astype(np.float32)
+    pts = rng.uniform(0, 1, size=(512, 3)).astype(np.float32)
     with smrt.MLP(max_batch=1024) as net:
-        net.set_params(torch.tensor(params, dtype=torch.float32, device="cuda:0"),
-                       torch.tensor(B, dtype=torch.float32, device="cuda:0"))
-        assert np.array_equal(net.get_params().cpu().numpy(), params.astype(np.float32))
-        y = net.forward(torch.tensor(pts, dtype=torch.float32, device="cuda:0")).cpu().numpy()
-    want, _ = M.forward(params.astype(np.float32), B.astype(np.float32), pts.astype(np.float32), dims)
-    rel = np.linalg.norm(y - want) / np.linalg.norm(want)
-    print("forward rel L2 error vs FP64: %.3e" % rel)
-    assert rel < 2e-2
+        net.set_params(torch.tensor(params, device="cuda:0"), torch.tensor(B, device="cuda:0"))
+        assert np.array_equal(net.get_params().cpu().numpy(), params)
+        y = net.forward(torch.tensor(pts, device="cuda:0")).cpu().numpy().astype(np.float64)
+    want, tol = M.forward_tolerance(params, B, pts, dims)
+    used = np.abs(y - want) / tol
+    plain, _ = M.forward(params, B, pts, dims)
+    print("forward: largest fraction of the tolerance used %.3f; median |dy|/|y| %.2e "
+          "(FP64 network: %.2e)" % (used.max(), np.median(np.abs(y - want) / np.abs(want)),
+                                    np.median(np.abs(y - plain) / np.abs(plain))))
+    assert np.all(used <= 1.0), np.argwhere(used > 1.0)[:10]
 
 
 @pytest.mark.parametrize("n", [1024, 65536])   # 8 and 512 row splits of the weight gradients
 def test_gradient_matches_oracle(smrt, n):
+    """All 54,531 gradient entries and the loss within their tolerances of the
+    bfloat16/binary32 model (oracle/mlp_oracle.py gradient_tolerance)."""
     rng = np.random.default_rng(2)
     dims, params, B = make_net(rng)
+    params, B = params.astype(np.float32), B.astype(np.float32)
     pts = rng.uniform(0, 1, size=(n, 3)).astype(np.float32)
     tgt = rng.normal(0, 0.5, size=(n, 3)).astype(np.float32)
     with smrt.MLP(max_batch=n) as net:
-        net.set_params(torch.tensor(params, dtype=torch.float32, device="cuda:0"),
-                       torch.tensor(B, dtype=torch.float32, device="cuda:0"))
+        net.set_params(torch.tensor(params, device="cuda:0"), torch.tensor(B, device="cuda:0"))
         loss, g = net.gradient(torch.tensor(pts, device="cuda:0"), torch.tensor(tgt, device="cuda:0"))
         g = g.cpu().numpy().astype(np.float64)
-    want_loss, want = M.loss_and_grad(params.astype(np.float32), B.astype(np.float32), pts, tgt, dims)
-    rel = np.linalg.norm(g - want) / np.linalg.norm(want)
-    cos = g @ want / (np.linalg.norm(g) * np.linalg.norm(want))
-    print("gradient rel L2 error %.3e, cosine %.6f, loss %.6f vs %.6f" % (rel, cos, loss, want_loss))
-    assert abs(loss / want_loss - 1) < 1e-2
-    assert rel < 3e-2 and cos > 0.9995
+    want_loss, loss_tol, want, tol = M.gradient_tolerance(params, B, pts, tgt, dims, GRADIENT_DEPTH)
+    assert g.shape == want.shape == (54531,)
+    used = np.abs(g - want) / tol
+    scale = np.abs(want) + 1e-3 * np.abs(want).max()
+    print("gradient: largest fraction of the tolerance used %.3f, median tolerance / |g| %.2e; "
+          "loss %.8f vs %.8f (tolerance %.1e)" % (used.max(), np.median(tol / scale), loss, want_loss, loss_tol))
+    assert np.all(used <= 1.0), np.argwhere(used > 1.0)[:10]
+    # the loss is summed in FP64 from binary32 errors in a block order
+    assert abs(loss - want_loss) <= loss_tol + 1e-12 * want_loss
 
 
 def to_bf16_bits(a):
