@@ -7,13 +7,18 @@ bandwidth-scale case: a 4096 x 4096 periodic Taylor-Green field (u0 = 0.05,
 wavenumber 2 pi / N, seeded +-1e-3 density noise), SmrtLBM, FP32 deviation
 storage, tau = 0.6.
 
-Printed (one JSON line): MLUPS of the whole job, the algorithmic HBM rate of
-the stream-collide kernel against the 8 TB/s peak (its average launch time
-measured with HIP events on the stream it runs on; the default kernel
-advances two time steps per launch through LDS, reading and writing each
-node's populations once per launch), the HBM bytes that the rocprofv3
-counters recorded for that kernel (when they were taken on the current kernel
-source), and the CPU oracle timed on a bounded sample of the same workload.
+Printed (one JSON line): MLUPS of the whole job; the roofline of the
+stream-collide kernel (its average launch time measured with HIP events on
+the stream it runs on; the default kernel advances five time steps per launch
+through LDS, reading and writing each node's populations once per launch):
+the algorithmic HBM rate against the 8 TB/s peak, the HBM bytes that the
+rocprofv3 counters recorded, and the vector-instruction rate against the
+issue ceiling (the counter figures when they were taken on the current
+kernel source), with "bound" naming the ceiling that binds; the CPU oracle
+timed on a bounded sample of the same workload; and, after the timed
+region, the rest of the metric: the rates of the other (scheme, tau) pairs,
+the 1024^2 cavity's time to the steady-state residual, and the learned warm
+start against the cold start.
 """
 import argparse
 import hashlib
@@ -33,7 +38,13 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2409_01076_amd", "csrc", f)
                   for f in ("lbm_kernels.hpp", "smrt_api.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_collide.json")
-STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_stream_collide.json")
+# Vector-instruction issue ceiling of the MI355X: 256 CUs x 4 SIMDs, one
+# 64-lane wave instruction per SIMD every 4 cycles (16 lanes per cycle) at
+# 2.4 GHz.  Packed FP32 instructions are disabled in this build, so every
+# FP32 operation is one such instruction.
+VALU_PEAK_G = 256 * 4 * 2.4 / 4
+STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2, "f32x": 4}
 
 
 def kernel_source_hash():
@@ -54,7 +65,7 @@ def parse():
     ap.add_argument("--window", type=int, default=1000, help="time steps per residual window")
     ap.add_argument("--n", type=int, default=4096, help="lattice side")
     ap.add_argument("--scheme", default="smrt", choices=["smrt", "srt", "trt"])
-    ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f16", "bf16"])
+    ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f16", "bf16", "f32x"])
     ap.add_argument("--tau", type=float, default=0.6)
     ap.add_argument("--launch", default="", help="bx,by,rows of the stream-collide kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -79,6 +90,9 @@ def parse():
     ap.add_argument("--re", type=float, default=1000.0, help="cavity Reynolds number")
     ap.add_argument("--tol", type=float, default=1e-7, help="cavity steady-state residual")
     ap.add_argument("--max-steps", type=int, default=3_000_000, help="cavity step cap")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default workload only: skip the six (scheme, tau) rates, the 1024^2 cavity's "
+                         "time to steady and the warm-start study")
     ap.add_argument("--copy-only", type=int, default=0, metavar="MIB",
                     help="only run the reference copy kernel over MIB mebibytes (counter calibration)")
     return ap.parse_args()
@@ -130,6 +144,46 @@ def traffic_record(launch_cells, kernel):
     if rec.get("cells_per_launch") != launch_cells or rec.get("kernel_name") != kernel:
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def valu_record(launch_cells):
+    """VALU wave instructions per launch of the multi-step kernel and per
+    node-update of the one-step kernel, from the committed counter record,
+    or None when it is missing, describes another lattice, or was taken on
+    other kernel source."""
+    try:
+        with open(VALU_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash() or rec.get("cells") != launch_cells:
+        return None
+    return rec
+
+
+def pair_rates(n, steps=1000, storages=("f32",)):
+    """GLUPS of the default launch for every (scheme, tau) of the bandwidth
+    workload: `steps` time steps timed with HIP events on the solver's stream
+    after 100 untimed ones."""
+    import torch
+    from paper_2409_01076_amd import inputs, smrt
+    fields = [torch.from_numpy(a).to("cuda:0") for a in inputs.taylor_green(n, n, u0=0.05, noise=1e-3)]
+    out = {}
+    for storage in storages:
+        for scheme in ("smrt", "srt"):
+            for tau in (0.51, 0.6, 1.0):
+                with smrt.Solver(n, n, scheme=scheme, boundary="periodic", storage=storage, tau=tau) as s:
+                    s.init_fields(*fields)
+                    s.step(100)
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(s.stream)
+                    s.step(steps)
+                    e1.record(s.stream)
+                    torch.cuda.synchronize()
+                    out["%s %s tau=%g" % (storage, scheme, tau)] = round(
+                        n * n * steps / (e0.elapsed_time(e1) / 1e3) / 1e9, 2)
+    del fields
+    return out
 
 
 def cpu_baseline(args, fields, budget_s):
@@ -239,18 +293,20 @@ def small_cavity(args):
     print(json.dumps(out))
 
 
-def cavity_to_steady(args):
+def cavity_to_steady(args, storage=None, quiet=False):
     """Cold-start lid-driven cavity (U = 0.1) run until the windowed residual
-    falls below args.tol: steps, wall time and throughput for each scheme."""
+    falls below args.tol: steps, wall time and throughput for each scheme.
+    Returns the JSON record."""
     import torch
     from paper_2409_01076_amd import smrt
     n = args.n if args.n != 4096 else 1024
+    storage = storage or args.storage
     results = {}
     stages = []
     if args.schedule:
         first, level = args.schedule.split(":")
         stages.append((first, float(level)))
-    stages.append((args.storage, args.tol))
+    stages.append((storage, args.tol))
     for scheme in ("smrt", "srt"):
         solver = smrt.Solver(n, n, scheme=scheme, boundary="cavity", storage=stages[0][0],
                              re=args.re, u_lid=0.1, device="cuda:0")
@@ -261,7 +317,7 @@ def cavity_to_steady(args):
         last = [0.0]
 
         def progress(steps, r):
-            if time.perf_counter() - last[0] > 20:
+            if not quiet and time.perf_counter() - last[0] > 20:
                 last[0] = time.perf_counter()
                 print("# %s step %d residual %.3e" % (scheme, steps, r), file=sys.stderr, flush=True)
         steps, res, status, stage_steps = 0, [], "cap", []
@@ -294,18 +350,18 @@ def cavity_to_steady(args):
         "metric": METRIC, "value": s["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": s["steps"],
         "warmup": 0, "ms_per_step": round(s["seconds"] / max(1, s["steps"]) * 1e3, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.storage == "f64" else "f32", "data": "synthetic",
+        "dtype": "f64" if storage in ("f64", "f32x") else "f32", "data": "synthetic",
         "config": {"workload": "lid-driven cavity %dx%d, Re=%g, U=0.1, %s storage%s, cold start, "
                                "run to windowed residual < %g (window %d)"
-                               % (n, n, args.re, args.storage,
+                               % (n, n, args.re, storage,
                                   " after " + args.schedule if args.schedule else "", args.tol,
                                   args.window),
                    "schedule": args.schedule or None,
-                   "nx": n, "ny": n, "re": args.re, "u_lid": 0.1, "storage": args.storage,
+                   "nx": n, "ny": n, "re": args.re, "u_lid": 0.1, "storage": storage,
                    "window": args.window, "tol": args.tol},
         "time_to_steady": results,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def precision_study(args):
@@ -319,7 +375,7 @@ def precision_study(args):
     n = args.n if args.n != 4096 else 2048
     U = 0.1
     ref, out = None, {}
-    for storage in ("f64", "f32", "f16", "bf16"):
+    for storage in ("f64", "f32x", "f32", "f16", "bf16"):
         s = smrt.Solver(n, n, scheme=args.scheme, boundary="cavity", storage=storage, re=args.re,
                         u_lid=U, device="cuda:0")
         torch.cuda.synchronize()
@@ -418,7 +474,7 @@ def batch_to_steady(args):
     print(json.dumps(out), flush=True)
 
 
-def warm_start_study(args):
+def warm_start_study(args, quiet=False):
     """Learned warm start on 256^2 cavities: Re log-uniform in [100, 1e4]
     (seeded); args.train steady fields from the solver train the network on
     the GPU; on args.held_out other Re the cold start and the warm start run
@@ -431,7 +487,7 @@ def warm_start_study(args):
     rng = np.random.default_rng(2409010760)
     re_all = 100.0 * 100.0 ** rng.uniform(0, 1, size=args.train + args.held_out)
     re_train, re_test = re_all[:args.train], re_all[args.train:]
-    log = lambda msg: print("# " + msg, file=sys.stderr, flush=True)
+    log = (lambda msg: None) if quiet else (lambda msg: print("# " + msg, file=sys.stderr, flush=True))
 
     def run_batch(res, warm=None):
         b = smrt.Batch([n] * len(res), [n] * len(res), scheme=args.scheme, storage=args.storage,
@@ -493,7 +549,7 @@ def warm_start_study(args):
         "total_seconds": round(time.perf_counter() - t0, 1),
         "per_cavity": per,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def main():
@@ -512,7 +568,7 @@ def main():
         return
 
     if args.workload == "cavity":
-        cavity_to_steady(args)
+        print(json.dumps(cavity_to_steady(args)), flush=True)
         return
     if args.workload == "precision":
         precision_study(args)
@@ -521,7 +577,7 @@ def main():
         batch_to_steady(args)
         return
     if args.workload == "warmstart":
-        warm_start_study(args)
+        print(json.dumps(warm_start_study(args)), flush=True)
         return
     if args.workload == "small":
         small_cavity(args)
@@ -595,6 +651,10 @@ def main():
     achieved = alg_bytes / (launch_ms / 1e3) / 1e9
     mlups = cells * K * args.steps / wall / 1e6
     traffic = traffic_record(cells, kernel_name)
+    hbm_frac = achieved / HBM_PEAK_GBS
+    valu = valu_record(cells) if args.scheme == "smrt" and args.storage == "f32" and spl > 1 else None
+    if valu is not None and valu.get("multi_kernel_name") != kernel_name:
+        valu = None
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -620,7 +680,7 @@ def main():
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "frac": round(hbm_frac, 4),
             "traffic": traffic,
             "kernel": kernel_name,
             "time_steps_per_launch": spl,
@@ -635,11 +695,60 @@ def main():
         "mass_drift": mass / mass0 - 1.0,
     }
     out["roofline"]["frac_of_copy_kernel"] = round(achieved / out["copy_kernel_gbs"], 4)
+    if valu is not None:
+        # The vector-instruction ceiling.  Algorithmic instructions: a node
+        # advanced spl steps costs spl times the one-step kernel's VALU
+        # instructions per node-update (its collision, streaming and
+        # addressing, no ring recomputation); issued: what the counters
+        # recorded for the multi-step launch (rings and LDS addressing too).
+        per_update = valu["one_step_wave_insts_per_launch"] / cells
+        alg_insts = per_update * spl * cells
+        alg_g = alg_insts / (launch_ms / 1e3) / 1e9
+        issued_g = valu["multi_wave_insts_per_launch"] / (launch_ms / 1e3) / 1e9
+        hbm = {k: out["roofline"][k] for k in ("achieved", "peak", "unit", "frac")}
+        out["roofline"]["hbm"] = hbm
+        out["roofline"]["valu"] = {
+            "achieved": round(alg_g, 1), "peak": VALU_PEAK_G, "unit": "G wave-instructions/s",
+            "frac": round(alg_g / VALU_PEAK_G, 4),
+            "algorithmic_wave_insts_per_launch": round(alg_insts),
+            "algorithmic_unit": "one node advanced %d time steps: %d x the one-step kernel's %.2f lane "
+                                "instructions per node-update" % (spl, spl, per_update * 64),
+            "issued_wave_insts_per_launch": valu["multi_wave_insts_per_launch"],
+            "issued_g": round(issued_g, 1), "issued_frac": round(issued_g / VALU_PEAK_G, 4),
+            "source": "SQ_INSTS_VALU, profiles/valu_stream_collide.json",
+        }
+        if issued_g / VALU_PEAK_G > hbm_frac:
+            # the vector ALU binds: report its ceiling at the top level
+            out["roofline"].update(bound="alu", achieved=round(alg_g, 1), peak=VALU_PEAK_G,
+                                   unit="G wave-instructions/s", frac=round(alg_g / VALU_PEAK_G, 4))
     # the HBM rate one step per launch would need for the same node updates:
     # temporal blocking moves 18 s / spl bytes per node-update instead of 18 s
     out["roofline"]["one_step_equivalent_gbs"] = round(achieved * spl, 1)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, fields, args.cpu_seconds)
+    if not args.no_extras:
+        # the rest of the metric, after the timed region: the other (scheme,
+        # tau) pairs of this workload, the 1024^2 cavity at Re 1000 from the
+        # cold start to the residual (binary32 storage with FP64 arithmetic,
+        # the storage that meets 1e-5 U against FP64, and with binary32
+        # arithmetic), and learned warm starts against cold starts
+        out["glups_pairs"] = pair_rates(n, storages=("f32", "f32x"))
+        import copy
+        cav = copy.copy(args)
+        cav.n, cav.schedule, cav.launch = 1024, "", ""
+        out["time_to_steady_cavity1024"] = {}
+        for storage in ("f32x", "f32"):
+            rec = cavity_to_steady(cav, storage=storage, quiet=True)
+            out["time_to_steady_cavity1024"][storage] = {
+                sch: {k: r[k] for k in ("steps", "seconds", "status", "final_residual", "mlups")}
+                for sch, r in rec["time_to_steady"].items()}
+        out["time_to_steady_cavity1024"]["config"] = ("lid-driven cavity 1024x1024, Re=%g, U=0.1, cold start, run to "
+                                                      "windowed residual < %g (window %d); f32x: binary32 storage "
+                                                      "with FP64 arithmetic" % (cav.re, cav.tol, cav.window))
+        ws = copy.copy(args)
+        ws.n, ws.max_steps, ws.storage = 256, 400_000, "f32"
+        rec = warm_start_study(ws, quiet=True)
+        out["warm_start"] = {k: v for k, v in rec.items() if k != "per_cavity"}
     print(json.dumps(out), flush=True)
 
 

@@ -69,7 +69,12 @@ typedef enum smrt_dtype {
     SMRT_F64 = 0,
     SMRT_F32 = 1,
     SMRT_F16 = 2, /* storage only: IEEE binary16 deviations, FP32 arithmetic */
-    SMRT_BF16 = 3 /* storage only: bfloat16 deviations, FP32 arithmetic      */
+    SMRT_BF16 = 3,/* storage only: bfloat16 deviations, FP32 arithmetic      */
+    SMRT_F32X = 4 /* storage only: binary32 deviations, FP64 arithmetic: each
+                     collision is computed in FP64 and rounded once per stored
+                     value, so the only FP32 error is the storage's own
+                     (binary32 collision arithmetic biases the momentum
+                     balance of a slowly converging cavity) */
 } smrt_dtype;
 
 typedef struct smrt_params {
@@ -77,7 +82,7 @@ typedef struct smrt_params {
     int32_t scheme;    /* smrt_scheme                                        */
     int32_t boundary;  /* smrt_boundary                                      */
     int32_t storage;   /* smrt_dtype of the stored populations; arithmetic is
-                          FP64 for SMRT_F64 and FP32 otherwise                */
+                          FP64 for SMRT_F64 and SMRT_F32X, FP32 otherwise     */
     int32_t reserved0; /* must be 0                                          */
     double tau;        /* > 1/2: used as given.  <= 0: derived from re as
                           tau = 3 |u_lid| nx / re + 1/2, i.e.
@@ -176,7 +181,8 @@ int smrt_set_launch(smrt_ctx* c, int32_t bx, int32_t by, int32_t rows);
  * unchanged: results are bitwise those of single-step launches.  Default at
  * creation: FP32 storage 5 steps with a 64 x 22 tile while that gives >= 1024
  * tiles or while 64 x 16 tiles would need between one and two waves of two
- * workgroups per CU, else with 64 x 16 while that gives >= 256; 16-bit storage 4 steps
+ * workgroups per CU, else with 64 x 16 while that gives >= 256 (SMRT_F32X as
+ * SMRT_F32); 16-bit storage 4 steps
  * with a 64 x 26 tile while that gives >= 1024 tiles or (as for FP32) avoids
  * a short second wave with its tiles in one wave, else with 64 x 16
  * while that gives >= 256; smaller lattices 4 steps with 64 x 8 tiles;
@@ -228,7 +234,9 @@ const char* smrt_last_error(void);
 typedef struct smrt_batch_params {
     int32_t count;        /* number of cavities, >= 1                          */
     int32_t scheme;       /* smrt_scheme                                       */
-    int32_t storage;      /* smrt_dtype of the stored populations              */
+    int32_t storage;      /* smrt_dtype of the stored populations: SMRT_F64,
+                             SMRT_F32, SMRT_F16 or SMRT_BF16 (SMRT_F32X is for
+                             single lattices only)                             */
     int32_t reserved0;    /* must be 0                                         */
     const int32_t* nx;    /* host array [count], each >= 3                     */
     const int32_t* ny;    /* host array [count], each >= 3                     */

@@ -31,16 +31,21 @@ struct bf16 {
 };
 
 // Storage traits: how a stored population d_a converts to and from the
-// arithmetic type C.  FP64 storage computes in FP64, everything else in FP32.
+// arithmetic type C.  FP64 storage and the FP32-storage/FP64-arithmetic type
+// (f32x) compute in FP64, everything else in FP32.
 //   load / store        the hot path (stores are non-temporal: written once,
 //                       read by the next step from HBM);
 //   stored_value(v, a)  v exactly as a store followed by a load returns it;
-//   to_f64 / from_f64   initialisation, export and reductions.
-// kRounds is true when stored_value is not the identity (16-bit storage).
+//   to_f64 / from_f64   initialisation, export and reductions;
+//   M                   the type a multi-step launch keeps its intermediate
+//                       steps in (LDS): C, or the stored type where C is
+//                       wider and every value is already on its grid.
+// kRounds is true when stored_value is not the identity.
 template <typename T> struct Storage;
 
 template <> struct Storage<double> {
     using C = double;
+    using M = double;
     static constexpr bool kRounds = false;
     static __device__ __forceinline__ C load(const double* p, int) { return *p; }
     static __device__ __forceinline__ void store(double* p, int, C v) { __builtin_nontemporal_store(v, p); }
@@ -51,6 +56,7 @@ template <> struct Storage<double> {
 
 template <> struct Storage<float> {
     using C = float;
+    using M = float;
     static constexpr bool kRounds = false;
     static __device__ __forceinline__ C load(const float* p, int) { return *p; }
     static __device__ __forceinline__ void store(float* p, int, C v) { __builtin_nontemporal_store(v, p); }
@@ -72,6 +78,7 @@ __device__ __forceinline__ float f16_unscale(int a)
 
 template <> struct Storage<_Float16> {
     using C = float;
+    using M = float;
     static constexpr bool kRounds = true;
     static __device__ __forceinline__ C load(const _Float16* p, int a) { return (float)*p * f16_unscale(a); }
     static __device__ __forceinline__ void store(_Float16* p, int a, C v)
@@ -106,6 +113,7 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float v)
 // bfloat16 keeps binary32's exponent range, so it needs no scaling.
 template <> struct Storage<bf16> {
     using C = float;
+    using M = float;
     static constexpr bool kRounds = true;
     static __device__ __forceinline__ C load(const bf16* p, int) { return bf16_to_f32(p->bits); }
     static __device__ __forceinline__ void store(bf16* p, int, C v)
@@ -115,6 +123,28 @@ template <> struct Storage<bf16> {
     static __device__ __forceinline__ C stored_value(C v, int) { return bf16_to_f32(f32_to_bf16(v)); }
     static __device__ __forceinline__ double to_f64(const bf16* p, int) { return (double)bf16_to_f32(p->bits); }
     static __device__ __forceinline__ void from_f64(bf16* p, int, double v) { p->bits = f32_to_bf16((float)v); }
+};
+
+// FP32 storage with FP64 arithmetic: every collision is computed in FP64
+// from the stored binary32 values and rounded once per stored value, so the
+// only FP32 error is that of the stored values themselves (binary32
+// arithmetic in the collision biases the momentum balance enough to move a
+// slowly converging cavity by 1e-5 of the lid speed within 2,000 steps).
+// Intermediate steps of a multi-step launch stay binary32 in LDS, exactly as
+// a store and load would leave them.
+struct f32x {
+    float v;
+};
+
+template <> struct Storage<f32x> {
+    using C = double;
+    using M = float;
+    static constexpr bool kRounds = true;
+    static __device__ __forceinline__ C load(const f32x* p, int) { return (double)p->v; }
+    static __device__ __forceinline__ void store(f32x* p, int, C v) { __builtin_nontemporal_store((float)v, &p->v); }
+    static __device__ __forceinline__ C stored_value(C v, int) { return (double)(float)v; }
+    static __device__ __forceinline__ double to_f64(const f32x* p, int) { return (double)p->v; }
+    static __device__ __forceinline__ void from_f64(f32x* p, int, double v) { p->v = (float)v; }
 };
 
 // D2Q9 in the paper's order; OPP[a] is the direction with e = -e_a.
@@ -515,8 +545,9 @@ __device__ __forceinline__ void ring_load(const T* __restrict__ src, const Geom&
 
 template <typename T, int SCHEME, int RX, int RY, int NT>
 __device__ __forceinline__ void ring_collide(const Coef<typename Storage<T>::C>& k, RingRegs<T, RX, RY, NT>& r,
-                                             typename Storage<T>::C (&m)[9][RY][RX])
+                                             typename Storage<T>::M (&m)[9][RY][RX])
 {
+    using M = typename Storage<T>::M;
 #pragma unroll
     for (int j = 0; j < RingRegs<T, RX, RY, NT>::P; ++j) {
         if (!r.live[j]) continue;
@@ -525,7 +556,7 @@ __device__ __forceinline__ void ring_collide(const Coef<typename Storage<T>::C>&
         collide<SCHEME, T>(r.d[j], k);
         if constexpr (Storage<T>::kRounds) r.d[j][0] = Storage<T>::stored_value(r.d[j][0], 0);
 #pragma unroll
-        for (int a = 0; a < 9; ++a) m[a][ly][lx] = r.d[j][a];
+        for (int a = 0; a < 9; ++a) m[a][ly][lx] = (M)r.d[j][a];
     }
 }
 
@@ -536,15 +567,16 @@ __device__ __forceinline__ void ring_collide(const Coef<typename Storage<T>::C>&
 // values, so their pulls need no wrap.  Every source is a constant offset
 // from the node's own cell.
 template <typename T, int BC, int FX, int FY, bool INNER = false>
-__device__ __forceinline__ void pull_lds(const typename Storage<T>::C (&m)[9][FY][FX], const Geom& g,
+__device__ __forceinline__ void pull_lds(const typename Storage<T>::M (&m)[9][FY][FX], const Geom& g,
                                          typename Storage<T>::C lid, int fx, int fy, int x, int y,
                                          typename Storage<T>::C d[9])
 {
     using C = typename Storage<T>::C;
+    using M = typename Storage<T>::M;
     constexpr int PL = FX * FY;
-    const C* own = &m[0][fy][fx];
+    const M* own = &m[0][fy][fx];
 #pragma unroll
-    for (int a = 0; a < 9; ++a) d[a] = own[a * PL - EY[a] * FX - EX[a]];
+    for (int a = 0; a < 9; ++a) d[a] = (C)own[a * PL - EY[a] * FX - EX[a]];
     if constexpr (BC == CAVITY && !INNER) {
         // only lanes on the lattice's outer ring have sources beyond a wall
         if ((x == 0) | (x == g.nx - 1) | (y == 0) | (y == g.ny - 1)) {
@@ -552,7 +584,7 @@ __device__ __forceinline__ void pull_lds(const typename Storage<T>::C (&m)[9][FY
             for (int a = 1; a < 9; ++a) {
                 const int sx = x - EX[a], sy = y - EY[a];
                 const bool inside = (unsigned)sx < (unsigned)g.nx && (unsigned)sy < (unsigned)g.ny;
-                const C back = own[OPP[a] * PL];
+                const C back = (C)own[OPP[a] * PL];
                 d[a] = inside ? d[a] : ((sy == g.ny) ? back + C(EX[a]) * lid : back);
             }
         }
@@ -565,7 +597,7 @@ __device__ __forceinline__ void pull_lds(const typename Storage<T>::C (&m)[9][FY
 template <typename T, int SCHEME, int BC, int TX, int TY, int NT, int R, bool INNER = false>
 __device__ __forceinline__ void lds_to_hbm(T* __restrict__ dst, const Geom& g, const Coef<typename Storage<T>::C>& k,
                                            int X0, int Y0,
-                                           const typename Storage<T>::C (&m)[9][TY + 2 * R][TX + 2 * R])
+                                           const typename Storage<T>::M (&m)[9][TY + 2 * R][TX + 2 * R])
 {
     using C = typename Storage<T>::C;
     const StoreBases<T> sb = store_bases(dst, g, Y0);
@@ -606,9 +638,9 @@ __device__ __forceinline__ void workgroup_tile(const Geom& g, int TX, int TY, in
 // window from (R - r, R - r), so a node has one frame position for every
 // step: it writes its new values where it pulled its own rest population.
 template <typename T, int TX, int TY, int S> struct MultiTile {
-    using C = typename Storage<T>::C;
+    using M = typename Storage<T>::M;
     static constexpr int R = S - 1, FX = TX + 2 * R, FY = TY + 2 * R;
-    C m[9][FY][FX];
+    M m[9][FY][FX];
 };
 
 // A middle step: pull from the ring-(r+1) step in LDS, collide on the tile
@@ -646,9 +678,9 @@ __device__ __forceinline__ void middle_step(const Geom& g, const Coef<typename S
         if (!live[j]) continue;
         const int i = threadIdx.x + j * NT;
         const int lx = i % BX, ly = i / BX;
-        C* own = &sh.m[0][ly + OFF][lx + OFF];
+        typename Storage<T>::M* own = &sh.m[0][ly + OFF][lx + OFF];
 #pragma unroll
-        for (int a = 0; a < 9; ++a) own[a * FX * FY] = d[j][a];
+        for (int a = 0; a < 9; ++a) own[a * FX * FY] = (typename Storage<T>::M)d[j][a];
     }
     __syncthreads();
 }

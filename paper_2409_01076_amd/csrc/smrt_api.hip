@@ -99,7 +99,8 @@ size_t elem_bytes(int storage)
 {
     switch (storage) {
     case SMRT_F64: return 8;
-    case SMRT_F32: return 4;
+    case SMRT_F32:
+    case SMRT_F32X: return 4;
     case SMRT_F16:
     case SMRT_BF16: return 2;
     default: return 0;
@@ -387,6 +388,7 @@ int dispatch_multi(smrt_ctx* c, int k, int cols, int rows, const void* src, void
     switch (c->p.storage) {
     case SMRT_F64: return launch_k_f64(c, k, rows, src, dst);
     case SMRT_F32: return launch_k<float>(c, k, cols, rows, src, dst);
+    case SMRT_F32X: return launch_k<smrt::f32x>(c, k, cols, rows, src, dst);
     case SMRT_F16: return launch_k<_Float16>(c, k, cols, rows, src, dst);
     default: return launch_k<smrt::bf16>(c, k, cols, rows, src, dst);
     }
@@ -397,6 +399,7 @@ int dispatch_step(smrt_ctx* c, const void* src, void* dst)
     switch (c->p.storage) {
     case SMRT_F64: return launch_step<double>(c, src, dst);
     case SMRT_F32: return launch_step<float>(c, src, dst);
+    case SMRT_F32X: return launch_step<smrt::f32x>(c, src, dst);
     case SMRT_F16: return launch_step<_Float16>(c, src, dst);
     default: return launch_step<smrt::bf16>(c, src, dst);
     }
@@ -408,6 +411,7 @@ template <typename Fn> int with_storage(smrt_ctx* c, void* buf, Fn&& fn)
     switch (c->p.storage) {
     case SMRT_F64: fn(static_cast<double*>(buf)); break;
     case SMRT_F32: fn(static_cast<float*>(buf)); break;
+    case SMRT_F32X: fn(static_cast<smrt::f32x*>(buf)); break;
     case SMRT_F16: fn(static_cast<_Float16*>(buf)); break;
     default: fn(static_cast<smrt::bf16*>(buf)); break;
     }
@@ -530,7 +534,8 @@ int smrt_create(const smrt_params* p, void* dev_ws, size_t ws_bytes, smrt_ctx** 
             // rings (~78 KB each) still fits an XCD's 4 MB L2 for the row
             // below; panels of 16 beyond (4096^2: 269.6 against 267.4)
             c->panel = cols <= 48 ? 48 : 16;
-            const int deep = p->storage == SMRT_F32 ? 5 : 4, tall = p->storage == SMRT_F32 ? 22 : 26;
+            const bool f32 = p->storage == SMRT_F32 || p->storage == SMRT_F32X;
+            const int deep = f32 ? 5 : 4, tall = f32 ? 22 : 26;
             // Two 768-thread workgroups are resident per CU (LDS), so a launch
             // runs in waves of 2 x CUs workgroups.  Where 64 x 16 tiles need
             // more than one wave but less than two, FP32's taller tiles avoid a
@@ -544,8 +549,7 @@ int smrt_create(const smrt_params* p, void* dev_ws, size_t ws_bytes, smrt_ctx** 
                 hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
                 cus = 256;
             const int64_t wave = 2 * (int64_t)cus;
-            const bool short_second_wave = tiles(16) > wave && tiles(16) < 2 * wave &&
-                                           (p->storage == SMRT_F32 || tiles(tall) <= wave);
+            const bool short_second_wave = tiles(16) > wave && tiles(16) < 2 * wave && (f32 || tiles(tall) <= wave);
             if ((tiles(tall) >= 1024 || short_second_wave) && fits(deep, tall)) {
                 c->fused = deep;
                 c->fused_rows = tall;

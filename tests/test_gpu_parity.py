@@ -16,7 +16,7 @@ from gpu_util import (gpu_fields, gpu_populations, max_vel_err, oracle_from_fiel
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": 1e-11, "f32": 1e-5}
+TOL = {"f64": 1e-11, "f32": 1e-5, "f32x": 1e-5}
 
 
 @pytest.fixture(scope="module")
@@ -26,7 +26,7 @@ def smrt():
 
 # --- the 64 x 64 cavity at Re = 100, 2000 steps, both schemes, FP64 and FP32 -------------
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f32x"])
 @pytest.mark.parametrize("scheme", ["smrt", "srt"])
 def test_cavity_64_re100_2000_steps(smrt, scheme, storage):
     n, u, steps = 64, 0.1, 2000
@@ -59,7 +59,7 @@ def test_one_step_from_nonequilibrium_populations(smrt, boundary, scheme, tau, t
     u = 0.08 if boundary == "cavity" else 0.0
     L = oracle_lattice(nx, ny, scheme, boundary, tau, u, tau_s)
     want = L.collide(oracle_from_post_collision(L, np.moveaxis(f0, 0, -1), 1))
-    for storage, tol in (("f64", 1e-15), ("f32", 2e-8)):
+    for storage, tol in (("f64", 1e-15), ("f32", 2e-8), ("f32x", 2e-8)):
         with smrt.Solver(nx, ny, scheme=scheme, boundary=boundary, storage=storage, tau=tau,
                          u_lid=u, tau_s=tau_s) as s:
             s.set_populations(to_dev(f0, torch.float64))
@@ -79,7 +79,7 @@ def test_periodic_taylor_green_ragged(smrt, scheme, tau):
     rho, ux, uy = inputs.taylor_green(nx, ny, u0=u0, noise=1e-3, seed=11)
     L = oracle_lattice(nx, ny, scheme, "periodic", tau, tau_s=0.8)
     o = L.fields(oracle_from_fields(L, rho, ux, uy, steps))
-    for storage in ("f64", "f32"):
+    for storage in ("f64", "f32", "f32x"):
         with smrt.Solver(nx, ny, scheme=scheme, boundary="periodic", storage=storage, tau=tau,
                          tau_s=0.8) as s:
             s.init_fields(to_dev(rho), to_dev(ux), to_dev(uy))
@@ -143,18 +143,60 @@ def test_taylor_green_4096_sampled(smrt, tg4096, scheme, tau):
     assert bool(torch.isfinite(ux1000).all())
 
 
-def test_taylor_green_4096_sampled_after_1000_steps(smrt, tg4096):
-    """The full config step count for the stiffest case, on one sampled node."""
-    rho, ux, uy = tg4096
-    scheme, tau = "smrt", 0.51
-    with smrt.Solver(TG_N, TG_N, scheme=scheme, boundary="periodic", storage="f32", tau=tau) as s:
+def tg_gpu_fields(smrt, fields, scheme, tau, storage, steps=1000):
+    rho, ux, uy = fields
+    n = rho.shape[0]
+    with smrt.Solver(n, n, scheme=scheme, boundary="periodic", storage=storage, tau=tau) as s:
         s.init_fields(to_dev(rho), to_dev(ux), to_dev(uy))
-        s.step(1000)
-        g = gpu_fields(s)
-    cell = [(1500, 2600)]
-    want = oracle_sample_periodic((scheme, tau, 1.0), rho, ux, uy, cell, 1000, chunk=50)
-    err = max(abs(g[1][cell[0]] - want[0, 1]), abs(g[2][cell[0]] - want[0, 2])) / TG_U0
-    print("tg4096 smrt tau=0.51 sampled @1000: %.3e" % err)
+        spl = s.steps_per_launch
+        s.step(steps)
+        return gpu_fields(s), spl
+
+
+@pytest.mark.timeout(900)
+def test_taylor_green_4096_full_field_bench_configuration(smrt, tg4096):
+    """The benchmark's workload in its launch configuration (4096^2 periodic
+    Taylor-Green, SmrtLBM, tau = 0.6, five steps per launch on 64 x 22 tiles):
+    every node against the full oracle run after the 1000 configured steps,
+    for FP32 and FP64 storage.  (The closed-form decay of the viscosity
+    relation is pinned on the oracle with a pressure-consistent initial field;
+    this workload starts from uniform density plus noise, whose acoustic
+    start-up transient, of period about N / 1.15 steps, dominates the mode's
+    amplitude over 1000 steps.)"""
+    scheme, tau, steps = "smrt", 0.6, 1000
+    print("case: tg4096 smrt tau=0.6 1000 steps, f32 and f64, full oracle", flush=True)
+    g32, spl = tg_gpu_fields(smrt, tg4096, scheme, tau, "f32", steps)
+    assert spl == 5
+    g64, _ = tg_gpu_fields(smrt, tg4096, scheme, tau, "f64", steps)
+    L = oracle_lattice(TG_N, TG_N, scheme, "periodic", tau)
+    o = L.fields(oracle_from_fields(L, *tg4096, steps))
+    err32, err64 = max_vel_err(g32, o) / TG_U0, max_vel_err(g64, o) / TG_U0
+    rho_err = float(np.abs(g32[0] - o[0]).max())
+    print("tg4096 smrt tau=0.6 @1000, every node: FP32 %.3e, FP64 %.3e of u0; FP32 max|drho| %.2e"
+          % (err32, err64, rho_err))
+    assert err32 <= TOL["f32"] and err64 <= TOL["f64"]
+
+
+@pytest.fixture(scope="module")
+def tg2048():
+    return inputs.taylor_green(2048, 2048, u0=TG_U0, noise=1e-3)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("scheme,tau", [("smrt", 0.51), ("smrt", 1.0), ("srt", 0.51), ("srt", 0.6),
+                                        ("srt", 1.0)])
+def test_taylor_green_2048_full_field_other_pairs(smrt, tg2048, scheme, tau):
+    """The other five (scheme, tau) pairs of the bandwidth workload, on 2048^2
+    (the same five-step 64 x 22 kernel as 4096^2): every node against the
+    full oracle run after 1000 steps."""
+    steps = 1000
+    print("case: tg2048 %s tau=%g 1000 steps f32, full oracle" % (scheme, tau), flush=True)
+    g32, spl = tg_gpu_fields(smrt, tg2048, scheme, tau, "f32", steps)
+    assert spl == 5
+    L = oracle_lattice(2048, 2048, scheme, "periodic", tau)
+    o = L.fields(oracle_from_fields(L, *tg2048, steps))
+    err = max_vel_err(g32, o) / TG_U0
+    print("tg2048 %s tau=%g @1000, every node: FP32 %.3e of u0" % (scheme, tau, err))
     assert err <= TOL["f32"]
 
 
@@ -348,7 +390,7 @@ def test_convert_between_storage_types(smrt):
 
 # --- two time steps per launch (LDS-blocked kernel) ----------------------------------------
 
-@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16", "f32x"])
 @pytest.mark.parametrize("boundary", ["periodic", "cavity"])
 @pytest.mark.parametrize("scheme", ["srt", "smrt", "trt"])
 @pytest.mark.parametrize("tile", [(64, 4), (64, 8), (64, 16), (64, 32), (128, 4), (128, 8)])
@@ -424,7 +466,7 @@ def test_multi_step_kernel_fp64_equals_single_steps(smrt, boundary, scheme, mult
         assert np.array_equal(outs[0], outs[1])
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16", "f32x"])
 @pytest.mark.parametrize("boundary", ["periodic", "cavity"])
 @pytest.mark.parametrize("scheme", ["srt", "smrt", "trt"])
 @pytest.mark.parametrize("tile", [(64, 8), (64, 16), (64, 26)])
@@ -450,7 +492,7 @@ def test_multi_step_kernel_equals_single_steps(smrt, storage, boundary, scheme, 
         assert np.array_equal(outs[0], outs[1])
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16", "f32x"])
 @pytest.mark.parametrize("boundary", ["periodic", "cavity"])
 @pytest.mark.parametrize("scheme", ["srt", "smrt", "trt"])
 @pytest.mark.parametrize("tile", [(64, 16), (64, 22)])
@@ -476,7 +518,7 @@ def test_five_step_kernel_equals_single_steps(smrt, storage, boundary, scheme, t
 
 @pytest.mark.parametrize("nx,ny", [(3, 3), (5, 70), (13, 21), (64, 64), (65, 9)])
 @pytest.mark.parametrize("multi", [3, 4, 5])
-@pytest.mark.parametrize("storage", ["f32", "f64"])
+@pytest.mark.parametrize("storage", ["f32", "f64", "f32x"])
 def test_multi_step_kernel_small_cavities(smrt, nx, ny, multi, storage):
     if storage == "f64" and multi == 5:
         pytest.skip("FP64 storage runs at most four steps per launch")
@@ -530,7 +572,8 @@ def test_three_step_kernel_rejects_unsupported(smrt):
 
 
 @pytest.mark.parametrize("n,boundary,steps,storage", [(4096, "periodic", 402, "f32"), (1024, "cavity", 4001, "f32"),
-                                                     (1024, "cavity", 1001, "f64"), (2048, "periodic", 402, "f16")])
+                                                     (1024, "cavity", 1001, "f64"), (2048, "periodic", 402, "f16"),
+                                                     (1024, "cavity", 4001, "f32x")])
 def test_default_launch_long_run_bitwise(smrt, n, boundary, steps, storage):
     """The default launch configuration (FP32 five steps per launch: 64 x 22
     tiles on 4096^2, 64 x 16 on 1024^2; FP16 four steps with 64 x 26 tiles;
@@ -544,7 +587,7 @@ def test_default_launch_long_run_bitwise(smrt, n, boundary, steps, storage):
             if boundary == "periodic":
                 s.init_fields(*(to_dev(a) for a in inputs.taylor_green(n, n)))
             if default:
-                assert s.steps_per_launch == (5 if storage == "f32" else 4)
+                assert s.steps_per_launch == (5 if storage in ("f32", "f32x") else 4)
             else:
                 s.set_steps_per_launch(1)
             s.step(steps)
@@ -610,22 +653,55 @@ def test_graph_captured_steps_match_eager(smrt, n, storage):
     replay.close()
 
 
+def cavity_1024_fields(smrt, scheme, storage, steps=20_000, n=1024, re=1000.0, u=0.1):
+    with smrt.Solver(n, n, scheme=scheme, storage=storage, re=re, u_lid=u) as s:
+        s.step(steps)
+        mass = s.mass()
+        return s.moments(torch.float64), mass / n / n - 1
+
+
+@pytest.fixture(scope="module")
+def cavity_1024_fp64():
+    """GPU FP64 fields of the 1024^2 cavity at Re 1000 after 20,000 steps
+    (FP64 storage holds to the oracle at round-off)."""
+    smrt = require_gpu()
+    out = {}
+    for scheme in ("smrt", "srt"):
+        fields, drift = cavity_1024_fields(smrt, scheme, "f64")
+        assert abs(drift) < 1e-12
+        out[scheme] = fields
+    return out
+
+
 @pytest.mark.parametrize("scheme", ["smrt", "srt"])
-def test_cavity_1024_re1000_fp32_against_fp64_20k_steps(smrt, scheme):
-    """The 1024^2 cavity at Re = 1000 over 20,000 steps: FP32 storage against
-    FP64 storage on the GPU (which holds to the oracle at round-off).  FP32
-    rounding accumulates in the slowly decaying modes, so the bound is looser
-    than the 1e-5 U of the short runs: measured 3.6e-5 (SmrtLBM) and 4.5e-5
-    (SRT) of U at 20,000 steps, 2.3e-4 at the steady state (393,000 steps)."""
-    n, re, u, steps = 1024, 1000.0, 0.1, 20_000
-    fields = {}
-    for storage in ("f64", "f32"):
-        with smrt.Solver(n, n, scheme=scheme, storage=storage, re=re, u_lid=u) as s:
-            s.step(steps)
-            fields[storage] = s.moments(torch.float64)
-            mass = s.mass()
-        assert abs(mass / n / n - 1) < (1e-12 if storage == "f64" else 1e-9)
-    a, b = fields["f64"], fields["f32"]
-    err = max(float((a[1] - b[1]).abs().max()), float((a[2] - b[2]).abs().max())) / u
-    print("cavity1024 Re1000 %s 20k steps: FP32 vs FP64 max|du|/U = %.3e" % (scheme, err))
-    assert err <= 1e-4
+def test_cavity_1024_re1000_fp32_against_fp64_20k_steps(smrt, cavity_1024_fp64, scheme):
+    """The 1024^2 cavity at Re = 1000 over 20,000 steps with binary32 storage
+    and FP64 collision arithmetic (the storage the cavity workload takes)
+    against FP64 storage: within 1e-5 of U (measured 1e-7).  A float32 CPU
+    emulation put the error of binary32 storage alone at 9.0e-8 U here,
+    against 4.7e-5 U with binary32 arithmetic."""
+    print("case: cavity1024 Re1000 %s f32x 20k steps" % scheme, flush=True)
+    (_, ux, uy), drift = cavity_1024_fields(smrt, scheme, "f32x")
+    a = cavity_1024_fp64[scheme]
+    err = max(float((a[1] - ux).abs().max()), float((a[2] - uy).abs().max())) / 0.1
+    print("cavity1024 Re1000 %s 20k steps: FP32 storage + FP64 arithmetic vs FP64: max|du|/U = %.3e, "
+          "mass drift %.1e" % (scheme, err, drift))
+    assert err <= TOL["f32x"]
+    assert abs(drift) < 1e-9
+
+
+@pytest.mark.xfail(strict=True, reason="binary32 collision arithmetic biases the momentum balance: "
+                                       "3.6e-5 (SmrtLBM) and 4.5e-5 (SRT) of U at 20,000 steps; "
+                                       "FP32 storage with FP64 arithmetic meets the bound")
+@pytest.mark.parametrize("scheme", ["smrt", "srt"])
+def test_cavity_1024_re1000_fp32_arithmetic_20k_steps(smrt, cavity_1024_fp64, scheme):
+    """The same run with binary32 collision arithmetic (the fast FP32 path)
+    does not meet 1e-5 of U: kept as a strict expected failure."""
+    print("case: cavity1024 Re1000 %s f32 20k steps" % scheme, flush=True)
+    (_, ux, uy), drift = cavity_1024_fields(smrt, scheme, "f32")
+    a = cavity_1024_fp64[scheme]
+    err = max(float((a[1] - ux).abs().max()), float((a[2] - uy).abs().max())) / 0.1
+    print("cavity1024 Re1000 %s 20k steps: FP32 arithmetic vs FP64: max|du|/U = %.3e" % (scheme, err))
+    assert abs(drift) < 1e-9
+    assert err <= 1e-4         # the measured level, not the bound
+    assert err <= TOL["f32"]
