@@ -15,7 +15,8 @@ Which passage each function follows:
   stream           left-hand side of those equations (f moves along e_a),
                    with the "standard bounce-back" walls and the moving lid of
                    the cavity section (readings: half-way walls, moving-wall
-                   correction with rho_w = 1, lid owns the corner links)
+                   correction with rho_w = 1, lid owns the corner links; or
+                   the second lid reading, an equilibrium lid on the top row)
   tau_from_re      Eq. (relation-chapman-viscosity) with Re = U N / nu
   reduce           sums for the steady-state residual (a reading; the paper
                    does not define its steady-state test)
@@ -39,6 +40,7 @@ class _Lattice(ctypes.Structure):
         ("periodic_x", ctypes.c_int), ("periodic_y", ctypes.c_int),
         ("scheme", ctypes.c_int),
         ("tau", ctypes.c_double), ("tau_s", ctypes.c_double), ("u_lid", ctypes.c_double),
+        ("lid", ctypes.c_int),
     ]
 
 
@@ -137,11 +139,14 @@ class Lattice:
 
     ``boundary`` is 'periodic' (both axes wrap), 'cavity' (walls on all four
     sides, the top one moving at ``u_lid``) or 'channel' (x wraps, walls at
-    the bottom and top, the top moving at ``u_lid``).
+    the bottom and top, the top moving at ``u_lid``).  ``lid`` is 'wall'
+    (moving-wall bounce-back half a link above the top row) or 'equilibrium'
+    (the top row is the lid, set each step to the equilibrium at (u_lid, 0)
+    with the density its incoming populations give).
     """
 
     def __init__(self, nx, ny, scheme="smrt", tau=None, re=None, u_lid=0.0,
-                 boundary="cavity", tau_s=1.0):
+                 boundary="cavity", tau_s=1.0, lid="wall"):
         if tau is None:
             if re is None:
                 raise ValueError("give tau or re")
@@ -150,8 +155,9 @@ class Lattice:
         self.nx, self.ny = int(nx), int(ny)
         self.scheme, self.tau, self.tau_s = scheme, float(tau), float(tau_s)
         self.u_lid, self.boundary = float(u_lid), boundary
+        self.lid = lid
         self._c = _Lattice(self.nx, self.ny, px, py, SCHEMES[scheme], self.tau, self.tau_s,
-                           self.u_lid)
+                           self.u_lid, {"wall": 0, "equilibrium": 1}[lid])
 
     @property
     def shape(self):

@@ -128,6 +128,7 @@ static int lattice_ok(const oracle_lattice* L)
     if (!(L->tau > 0.5)) return 0;
     if (L->scheme < ORACLE_SRT || L->scheme > ORACLE_TRT) return 0;
     if (L->scheme == ORACLE_TRT && !(L->tau_s > 0.5)) return 0;
+    if (L->lid != 0 && (L->lid != 1 || L->periodic_y || L->ny < 2)) return 0;
     return 1;
 }
 
@@ -151,13 +152,30 @@ int oracle_collide_lattice(const oracle_lattice* L, const double* f, double* fst
     return 0;
 }
 
+/* Second lid reading: the top row holds the lid.  Each of its nodes is set
+ * to f^eq(rho, (u_lid, 0)) with rho from the populations that arrived from
+ * inside the cavity: for a wall moving along itself (u_y = 0) the unknown
+ * f_4, f_7, f_8 carry as much mass as the f_2, f_5, f_6 that left, so
+ * rho = f_0 + f_1 + f_3 + 2 (f_2 + f_5 + f_6).  Applied after streaming; what
+ * streaming wrote into f_4, f_7, f_8 of the top row is overwritten. */
+static void apply_equilibrium_lid(const oracle_lattice* L, double* f)
+{
+    const int nx = L->nx, y = L->ny - 1;
+    for (int x = 0; x < nx; ++x) {
+        double* g = f + 9 * ((long)y * nx + x);
+        double rho = g[0] + g[1] + g[3] + 2.0 * (g[2] + g[5] + g[6]);
+        oracle_equilibrium(rho, L->u_lid, 0.0, g);
+    }
+}
+
 /* Left-hand side of every update equation: the post-collision population
  * f*_a(x) moves to x + e_a.  If x + e_a lies beyond a wall, the population is
  * bounced back into the opposite direction at x (half-way bounce-back, the
  * wall sits half a link away).  A moving wall adds -2 w_a rho_w (e_a.u_w)/c_s^2
  * = -6 w_a (e_a.u_w) with rho_w = 1 (moving-wall bounce-back).  A link whose
  * far end lies in the row above the top fluid row (corners included) ends on
- * the lid; every other wall is at rest. */
+ * the lid; every other wall is at rest.  With the second lid reading the
+ * top row is then set to the lid's equilibrium (apply_equilibrium_lid). */
 int oracle_stream_lattice(const oracle_lattice* L, const double* fstar, double* fnext)
 {
     if (!lattice_ok(L) || !fstar || !fnext || fstar == fnext) return -1;
@@ -193,6 +211,7 @@ int oracle_stream_lattice(const oracle_lattice* L, const double* fstar, double* 
             }
         }
     }
+    if (L->lid == 1) apply_equilibrium_lid(L, fnext);
     return 0;
 }
 

@@ -18,6 +18,12 @@
  *   - row y = 0 is the bottom; a non-periodic axis is closed by half-way
  *     bounce-back walls at -1/2 and n-1/2; the wall beyond the top row
  *     (y = ny) moves with velocity (u_lid, 0), every other wall is at rest.
+ *   - second lid reading (lid = 1, non-periodic y only): the top row of
+ *     nodes is the lid itself.  After each step its populations are set to
+ *     the equilibrium at velocity (u_lid, 0) and the density that the
+ *     populations it received from inside give for a wall moving along
+ *     itself, rho = f_0 + f_1 + f_3 + 2 (f_2 + f_5 + f_6); nothing streams
+ *     in from above.  The side and bottom walls stay half-way bounce-back.
  *
  * Error behaviour: functions returning int give 0 on success and -1 on an
  * invalid argument (NULL pointer, non-positive size, unknown scheme,
@@ -39,6 +45,9 @@ typedef struct oracle_lattice {
     double tau;                 /* relaxation time tied to viscosity      */
     double tau_s;               /* second relaxation time (TRT form only) */
     double u_lid;               /* x-velocity of the top wall             */
+    int lid;                    /* 0: moving wall half a link above the
+                                   top row; 1: equilibrium lid on the top
+                                   row (see above)                          */
 } oracle_lattice;
 
 /* Copies the lattice constants (velocities, weights, opposite directions). */
@@ -65,7 +74,8 @@ int oracle_init_equilibrium(const oracle_lattice* L, const double* rho,
 int oracle_collide_lattice(const oracle_lattice* L, const double* f, double* fstar);
 
 /* Streaming with walls: fnext_a(x + e_a) = fstar_a(x), bounced back where
- * x + e_a lies beyond a wall.  fstar and fnext must not overlap. */
+ * x + e_a lies beyond a wall; with lid = 1 the top row is then set to the
+ * lid's equilibrium.  fstar and fnext must not overlap. */
 int oracle_stream_lattice(const oracle_lattice* L, const double* fstar, double* fnext);
 
 /* nsteps of collide-then-stream, in place on f (pre-collision populations). */

@@ -199,6 +199,82 @@ def test_stability_contrast_srt_vs_smrt():
     assert np.isfinite(ux).all() and np.abs(ux).max() < 0.5
 
 
+# --- the second lid reading: an equilibrium lid on the top row -----------------------------
+
+@pytest.mark.parametrize("ny,U,tau", [(6, 0.1, 0.55), (6, 0.02, 2.0), (11, 0.1, 0.8), (11, 0.02, 1.3)])
+def test_equilibrium_lid_couette_closed_form(ny, U, tau):
+    """Couette flow between a half-way bounce-back wall at y = -1/2 and an
+    equilibrium lid on row ny-1, SRT.  With u = b (y + 1/2) the bulk
+    non-equilibrium part of each diagonal population is -tau b/12 (x-flux
+    -b (2 tau - 1)/6 = -nu b per link); the lid row sends its populations
+    down with none, so the flux across the last link is
+    u(ny-2)/6 - (tau - 1) b/6 - U/6.  Equating the two gives
+    b = U / (ny - 3/2 + tau): the fluid rows carry the linear profile
+    U (y + 1/2) / (ny - 3/2 + tau), the lid row exactly U."""
+    L = O.Lattice(4, ny, "srt", tau=tau, u_lid=U, boundary="channel", lid="equilibrium")
+    rho, ux, uy = L.fields(L.run(L.init_equilibrium(), 60000))
+    y = np.arange(ny - 1)
+    assert np.max(np.abs(ux[:-1] - (U * (y + 0.5) / (ny - 1.5 + tau))[:, None])) < 1e-13
+    assert np.max(np.abs(ux[-1] - U)) < 1e-15 and np.max(np.abs(uy)) < 1e-14
+
+
+def test_equilibrium_lid_first_steps_by_hand():
+    """From rest: after one step the lid row holds f^eq(1, (U, 0)) (the density
+    its incoming populations give is w_0 + w_1 + w_3 + 2 (w_2 + w_5 + w_6) = 1);
+    after two steps the row below has received from it
+    f_4 = (1 - 3U^2/2)/9, f_7 = (1 - 3U + 3U^2)/36, f_8 = (1 + 3U + 3U^2)/36, and
+    the lid row is again f^eq(1, (U, 0)) (f_0, f_1, f_3 from the lid row, f_2,
+    f_5, f_6 at rest: density 1), except at its corners, where the side wall
+    returns the corner's own moving f_3, f_7 (left) or f_1, f_8 (right) in
+    place of a neighbour's: density 1 - 5U/6 + U^2/6 (left) and
+    1 + 5U/6 + U^2/6 (right).  Everything else keeps its weight."""
+    U = 0.1
+    _, _, w, _ = O.constants()
+    shape = np.array([4 / 9 * (1 - 1.5 * U * U), (1 + 3 * U + 3 * U * U) / 9, (1 - 1.5 * U * U) / 9,
+                      (1 - 3 * U + 3 * U * U) / 9, (1 - 1.5 * U * U) / 9, (1 + 3 * U + 3 * U * U) / 36,
+                      (1 - 3 * U + 3 * U * U) / 36, (1 - 3 * U + 3 * U * U) / 36,
+                      (1 + 3 * U + 3 * U * U) / 36])     # f^eq(1, (U, 0)); f^eq(rho, .) = rho times it
+    feq_lid = shape
+    for scheme in ("srt", "smrt", "trt"):
+        L = O.Lattice(6, 5, scheme, tau=0.7, tau_s=0.9, u_lid=U, lid="equilibrium")
+        f1 = L.run(L.init_equilibrium(), 1)
+        want = np.broadcast_to(w, L.shape).copy()
+        want[-1] = feq_lid
+        assert np.max(np.abs(f1 - want)) < 4e-16
+        f2 = L.run(f1, 1)
+        want2 = np.broadcast_to(w, L.shape).copy()
+        want2[-1] = feq_lid
+        for a in (4, 7, 8):
+            want2[-2, :, a] = feq_lid[a]
+        # side walls: the corner nodes of row ny-2 get their wall-side diagonal
+        # by bounce-back of their own (resting) population instead
+        want2[-2, 0, 8] = w[8]
+        want2[-2, -1, 7] = w[7]
+        want2[-1, 0] = (1 - 5 * U / 6 + U * U / 6) * shape
+        want2[-1, -1] = (1 + 5 * U / 6 + U * U / 6) * shape
+        assert np.max(np.abs(f2 - want2)) < 4e-16, scheme
+
+
+@pytest.mark.parametrize("scheme", ["srt", "smrt"])
+def test_equilibrium_lid_mirror_symmetry_and_vortex(scheme):
+    """Reversing the lid mirrors the flow; the lid drives the same clockwise
+    vortex as the moving wall."""
+    a = O.Lattice(24, 20, scheme, tau=0.62, u_lid=0.1, lid="equilibrium")
+    b = O.Lattice(24, 20, scheme, tau=0.62, u_lid=-0.1, lid="equilibrium")
+    _, ax, ay = a.fields(a.run(a.init_equilibrium(), 800))
+    _, bx, by = b.fields(b.run(b.init_equilibrium(), 800))
+    assert np.max(np.abs(bx[:, ::-1] + ax)) < 1e-15
+    assert np.max(np.abs(by[:, ::-1] - ay)) < 1e-15
+    assert np.max(np.abs(ax[-1] - 0.1)) < 1e-15      # the lid row moves with the lid
+    assert ax[3].mean() < 0 and ay[:, 3].mean() > 0 > ay[:, -5].mean()
+
+
+def test_equilibrium_lid_needs_a_closed_top():
+    with pytest.raises(ValueError):
+        L = O.Lattice(8, 8, "smrt", tau=0.6, boundary="periodic", lid="equilibrium")
+        L.run(L.init_equilibrium(), 1)
+
+
 def test_reduce_sums_and_nonfinite_count():
     rho = np.array([1.0, 2.0, 3.0, 4.0])
     ux = np.array([0.0, 1.0, 0.0, 2.0])
