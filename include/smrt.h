@@ -61,8 +61,14 @@ typedef enum smrt_scheme {
 } smrt_scheme;
 
 typedef enum smrt_boundary {
-    SMRT_CAVITY = 0,  /* lid-driven square cavity of the paper's test section */
-    SMRT_PERIODIC = 1 /* both axes wrap around                                */
+    SMRT_CAVITY = 0,      /* lid-driven square cavity of the paper's test section */
+    SMRT_PERIODIC = 1,    /* both axes wrap around                                */
+    SMRT_CAVITY_EQLID = 2 /* the cavity under a second reading of its lid: the top
+                             row of nodes is the lid, set each step to
+                             f^eq(rho, (u_lid, 0)) (Eq. feq-full) with
+                             rho - 1 = d_0 + d_1 + d_3 + 2 (d_2 + d_5 + d_6) from the
+                             populations it received; side and bottom walls
+                             half-way bounce-back.  One time step per launch. */
 } smrt_boundary;
 
 typedef enum smrt_dtype {

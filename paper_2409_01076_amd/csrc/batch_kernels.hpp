@@ -49,6 +49,7 @@ template <typename C> __device__ __forceinline__ Coef<C> coef_of(const CavityDes
     k.a = (C)c.a;
     k.b = (C)c.b;
     k.lid = (C)c.lid;
+    k.ulid = (C)0; // the batch's lid is the moving wall
     return k;
 }
 

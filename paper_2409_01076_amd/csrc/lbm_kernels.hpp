@@ -23,7 +23,10 @@
 namespace smrt {
 
 enum { SRT = 0, SMRT = 1, TRT = 2 };
-enum { CAVITY = 0, PERIODIC = 1 };
+// CAVITY: half-way bounce-back walls, the lid a moving wall half a link above
+// the top row.  CAVITY_EQLID: the same walls, but the top row of nodes is the
+// lid itself (the second lid reading; one step per launch only).
+enum { CAVITY = 0, PERIODIC = 1, CAVITY_EQLID = 2 };
 
 // bfloat16 storage: the upper half of an IEEE binary32.
 struct bf16 {
@@ -212,6 +215,7 @@ template <typename C> struct Coef {
     C a;       // 1 - 1/tau (SmrtLBM)
     C b;       // 1/tau_s - 1/tau (TRT)
     C lid;     // 6 w_diag u_lid = u_lid / 6: the moving-lid term of a diagonal link
+    C ulid;    // u_lid itself (equilibrium lid)
 };
 
 // Moments, equilibrium deviation and collision of one node, in deviation form.
@@ -339,6 +343,29 @@ __device__ __forceinline__ void collide(C d[9], const Coef<C>& k)
         for (int a = 1; a < 9; ++a) d[a] = Storage<T>::stored_value(d[a], a);
     }
     d[0] = drho - (((d[1] + d[2]) + (d[3] + d[4])) + ((d[5] + d[6]) + (d[7] + d[8])));
+}
+
+// The equilibrium lid (second lid reading): a node of the top row is set to
+// f^eq(rho, (U, 0)) (Eq. feq-full), with rho from the populations it received
+// from inside the cavity.  For a wall moving along itself the unknown d_4,
+// d_7, d_8 carry as much mass as the d_2, d_5, d_6 that left, so
+// rho - 1 = d_0 + d_1 + d_3 + 2 (d_2 + d_5 + d_6) (the weights of that sum add up
+// to 1).  In deviation form, with e_x = +1, 0, -1:
+//   d_a = w_a (drho + rho (3 e_x U + 9/2 e_x^2 U^2 - 3/2 U^2)).
+template <typename T, typename C = typename Storage<T>::C>
+__device__ __forceinline__ void lid_equilibrium(C d[9], const Coef<C>& k)
+{
+    const C drho = (d[0] + (d[1] + d[3])) + C(2) * ((d[2] + d[5]) + d[6]);
+    const C rho = C(1) + drho, U = k.ulid;
+    const C base = drho - C(1.5) * rho * U * U;
+    const C quad = C(4.5) * rho * U * U, lin = C(3) * rho * U;
+    const C plus = base + (quad + lin), minus = base + (quad - lin);
+    d[0] = C(4.0 / 9.0) * base;
+    d[2] = d[4] = W<C>::axis * base;
+    d[1] = W<C>::axis * plus;
+    d[3] = W<C>::axis * minus;
+    d[5] = d[8] = W<C>::diag * plus;
+    d[6] = d[7] = W<C>::diag * minus;
 }
 
 // Interior pulls and stores address each direction's plane through a
@@ -472,16 +499,20 @@ __global__ void __launch_bounds__(1024) stream_collide(const T* __restrict__ src
     const PullBases<T> pb = pull_bases(src, g, ytile > 0 ? ytile - 1 : 0);
     const StoreBases<T> sb = store_bases(dst, g, ytile);
     const int y0 = ytile + threadIdx.y;
+    constexpr int GBC = BC == PERIODIC ? PERIODIC : CAVITY; // the equilibrium lid pulls like the cavity
     for (int r = 0; r < g.rows; ++r) {
         const int y = y0 + r * g.by;
         if (y >= g.ny) break;
         C d[9];
         const bool edge = (x == 0) | (x == g.nx - 1) | (y == 0) | (y == g.ny - 1);
         if (edge)
-            gather_edge<T, BC>(src, g, x, y, d, k.lid);
+            gather_edge<T, GBC>(src, g, x, y, d, k.lid);
         else
             gather_interior<T>(pb, g, x, y, d);
-        collide<SCHEME, T>(d, k);
+        if (BC == CAVITY_EQLID && y == g.ny - 1)
+            lid_equilibrium<T>(d, k); // d_4, d_7, d_8 pulled from beyond the lid are not used
+        else
+            collide<SCHEME, T>(d, k);
         scatter_store<T>(sb, g, x, y, d);
     }
 }

@@ -161,7 +161,7 @@ int check_params(const smrt_params* p, double* tau_out)
         return fail(SMRT_EINVAL, "lattice of %d x %d nodes is too large", p->nx, p->ny);
     if (p->scheme < SMRT_SCHEME_SRT || p->scheme > SMRT_SCHEME_TRT)
         return fail(SMRT_EINVAL, "unknown scheme %d", p->scheme);
-    if (p->boundary != SMRT_CAVITY && p->boundary != SMRT_PERIODIC)
+    if (p->boundary != SMRT_CAVITY && p->boundary != SMRT_PERIODIC && p->boundary != SMRT_CAVITY_EQLID)
         return fail(SMRT_EINVAL, "unknown boundary %d", p->boundary);
     if (elem_bytes(p->storage) == 0) return fail(SMRT_EINVAL, "unknown storage type %d", p->storage);
     if ((long long)p->nx * (long long)elem_bytes(p->storage) > smrt_host::kMaxRowBytes)
@@ -245,26 +245,31 @@ template <typename T> int launch_step(smrt_ctx* c, const void* src, void* dst)
     k.a = (C)(1.0 - omega);
     k.b = (C)(omega_s - omega);
     k.lid = (C)(c->p.boundary == SMRT_CAVITY ? c->p.u_lid / 6.0 : 0.0);
+    k.ulid = (C)(c->p.boundary == SMRT_CAVITY_EQLID ? c->p.u_lid : 0.0);
     const int tiles_y = (g.ny + g.by * g.rows - 1) / (g.by * g.rows);
     const int64_t blocks = (int64_t)g.tiles_x * tiles_y;
     if (blocks > std::numeric_limits<int>::max()) return fail(SMRT_EINVAL, "grid too large");
     dim3 grid((unsigned)blocks), block(g.bx, g.by);
     const T* s = static_cast<const T*>(src);
     T* d = static_cast<T*>(dst);
-    const bool per = c->p.boundary == SMRT_PERIODIC;
+    auto go = [&](auto scheme_tag) {
+        constexpr int SCHEME = decltype(scheme_tag)::value;
+        switch (c->p.boundary) {
+        case SMRT_PERIODIC:
+            smrt::stream_collide<T, SCHEME, smrt::PERIODIC><<<grid, block, 0, c->stream>>>(s, d, g, k);
+            break;
+        case SMRT_CAVITY_EQLID:
+            smrt::stream_collide<T, SCHEME, smrt::CAVITY_EQLID><<<grid, block, 0, c->stream>>>(s, d, g, k);
+            break;
+        default:
+            smrt::stream_collide<T, SCHEME, smrt::CAVITY><<<grid, block, 0, c->stream>>>(s, d, g, k);
+            break;
+        }
+    };
     switch (c->p.scheme) {
-    case SMRT_SCHEME_SRT:
-        if (per) smrt::stream_collide<T, smrt::SRT, smrt::PERIODIC><<<grid, block, 0, c->stream>>>(s, d, g, k);
-        else smrt::stream_collide<T, smrt::SRT, smrt::CAVITY><<<grid, block, 0, c->stream>>>(s, d, g, k);
-        break;
-    case SMRT_SCHEME_SMRT:
-        if (per) smrt::stream_collide<T, smrt::SMRT, smrt::PERIODIC><<<grid, block, 0, c->stream>>>(s, d, g, k);
-        else smrt::stream_collide<T, smrt::SMRT, smrt::CAVITY><<<grid, block, 0, c->stream>>>(s, d, g, k);
-        break;
-    default:
-        if (per) smrt::stream_collide<T, smrt::TRT, smrt::PERIODIC><<<grid, block, 0, c->stream>>>(s, d, g, k);
-        else smrt::stream_collide<T, smrt::TRT, smrt::CAVITY><<<grid, block, 0, c->stream>>>(s, d, g, k);
-        break;
+    case SMRT_SCHEME_SRT: go(std::integral_constant<int, smrt::SRT>{}); break;
+    case SMRT_SCHEME_SMRT: go(std::integral_constant<int, smrt::SMRT>{}); break;
+    default: go(std::integral_constant<int, smrt::TRT>{}); break;
     }
     return SMRT_OK;
 }
@@ -312,6 +317,7 @@ template <typename T, int STEPS, int TX, int TY> int launch_multi_tile(smrt_ctx*
     k.a = (C)(1.0 - omega);
     k.b = (C)(omega_s - omega);
     k.lid = (C)(c->p.boundary == SMRT_CAVITY ? c->p.u_lid / 6.0 : 0.0);
+    k.ulid = (C)0; // the multi-step kernels take the moving-wall lid only
     const int64_t blocks = (int64_t)g.tiles_x * tiles_y;
     if (blocks > std::numeric_limits<int>::max()) return fail(SMRT_EINVAL, "grid too large");
     const int n = (int)blocks;
@@ -569,6 +575,7 @@ int smrt_create(const smrt_params* p, void* dev_ws, size_t ws_bytes, smrt_ctx** 
                 if (fits(2, c->fused_rows)) c->fused = 2;
             }
         }
+        if (p->boundary == SMRT_CAVITY_EQLID) c->fused = 1; // one-step kernel only
         if (p->nx >= 512) {
             c->bx = 512; c->by = 1;
         } else if (p->nx >= 256) {
@@ -757,6 +764,8 @@ int smrt_set_steps_per_launch(smrt_ctx* c, int32_t steps, int32_t tile_cols, int
 {
     if (!c) return fail(SMRT_EINVAL, "context is NULL");
     if (steps < 1 || steps > 5) return fail(SMRT_EINVAL, "steps per launch must be 1 .. 5 (got %d)", steps);
+    if (steps > 1 && c->p.boundary == SMRT_CAVITY_EQLID)
+        return fail(SMRT_EINVAL, "the equilibrium lid runs one time step per launch");
     if (steps == 1) { // one step per launch has no tile: keep the multi-step one
         c->fused = 1;
         return SMRT_OK;

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libsmrt.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
 SCHEMES = {"srt": 0, "smrt": 1, "trt": 2}
-BOUNDARIES = {"cavity": 0, "periodic": 1}
+BOUNDARIES = {"cavity": 0, "periodic": 1, "cavity_eqlid": 2}
 STORAGE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3, "f32x": 4}
 _IO_DTYPES = {torch.float64: 0, torch.float32: 1}
 
@@ -196,7 +196,9 @@ class Solver:
     """One lattice on one GPU.
 
     Parameters mirror ``smrt_params``: ``scheme`` in {'srt', 'smrt', 'trt'},
-    ``boundary`` in {'cavity', 'periodic'}, ``storage`` in {'f64', 'f32',
+    ``boundary`` in {'cavity', 'periodic', 'cavity_eqlid'} ('cavity_eqlid': the
+    cavity with the equilibrium lid on its top row, one step per launch),
+    ``storage`` in {'f64', 'f32',
     'f16', 'bf16', 'f32x'} ('f32x': FP32 storage with FP64 collision
     arithmetic); give ``tau`` directly or ``re`` (then tau = 3 U N / Re + 1/2).
     The workspace is a torch uint8 tensor on ``device``; work goes to the

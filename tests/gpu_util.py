@@ -37,6 +37,11 @@ def gpu_populations(solver):
 
 
 def oracle_lattice(nx, ny, scheme, boundary, tau, u_lid=0.0, tau_s=1.0):
+    """The oracle lattice for a library boundary name ('cavity_eqlid': the
+    cavity under the equilibrium-lid reading)."""
+    if boundary == "cavity_eqlid":
+        return O.Lattice(nx, ny, scheme, tau=tau, u_lid=u_lid, boundary="cavity", tau_s=tau_s,
+                         lid="equilibrium")
     return O.Lattice(nx, ny, scheme, tau=tau, u_lid=u_lid, boundary=boundary, tau_s=tau_s)
 
 

@@ -10,6 +10,11 @@ on 100^2 (U_lat = 1/3) diverge within 5000 steps with SmrtLBM and with the
 two-relaxation-time form, in FP32 and FP64, whether the lid owns the corner
 links or not.  Those tests are strict xfails: they state the paper's claim and
 would flip if a change made the runs stable.
+
+Under the second lid reading (the top row of nodes is the lid, set each step
+to the equilibrium at the lid velocity; boundary 'cavity_eqlid') both runs
+reproduce: SmrtLBM stays finite (and unsteady) through 10^6 steps on 400^2 and
+200,000 steps on 100^2, while SRT diverges within 20,000 and 5,000 steps.
 """
 import numpy as np
 import pytest
@@ -86,5 +91,56 @@ def test_re1e4_250_srt_blows_up(smrt):
     with smrt.Solver(250, 250, scheme="srt", boundary="cavity", storage="f32", tau=0.51,
                      u_lid=u) as s:
         s.step(50_000)
+        with pytest.raises(smrt.UnstableError):
+            s.residual()
+
+
+# --- the same claims under the equilibrium-lid reading --------------------------------------
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_re1e5_400_tau0502_smrt_stable_equilibrium_lid(smrt, storage):
+    """Re = 10^5 on 400^2 with tau = 0.502 under the equilibrium lid: finite
+    over 10^6 steps, never steady."""
+    u = lid_speed(1e5, 0.502, 400)
+    with smrt.Solver(400, 400, scheme="smrt", boundary="cavity_eqlid", storage=storage, tau=0.502,
+                     u_lid=u) as s:
+        for _ in range(10):
+            s.step(100_000)
+            r = s.residual()
+            assert np.isfinite(r)
+        _, ux, uy = s.moments()
+        assert float(ux.abs().max()) < 0.5 and float(uy.abs().max()) < 0.5
+        assert r > 1e-6
+    print("Re 1e5, 400^2, equilibrium lid, %s: finite through 10^6 steps, R = %.2e" % (storage, r))
+
+
+def test_re1e5_400_tau0502_srt_blows_up_equilibrium_lid(smrt):
+    u = lid_speed(1e5, 0.502, 400)
+    with smrt.Solver(400, 400, scheme="srt", boundary="cavity_eqlid", storage="f32", tau=0.502,
+                     u_lid=u) as s:
+        s.step(20_000)
+        with pytest.raises(smrt.UnstableError):
+            s.residual()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_re1e4_100_tau051_smrt_stable_equilibrium_lid(smrt, storage):
+    """Re = 10^4 on 100^2 with tau = 0.51 (U_lat = 1/3) under the equilibrium
+    lid: finite over 200,000 steps."""
+    u = lid_speed(1e4, 0.51, 100)
+    with smrt.Solver(100, 100, scheme="smrt", boundary="cavity_eqlid", storage=storage, tau=0.51,
+                     u_lid=u) as s:
+        for _ in range(10):
+            s.step(20_000)
+            r = s.residual()
+            assert np.isfinite(r)
+    print("Re 1e4, 100^2, equilibrium lid, %s: finite through 200,000 steps, R = %.2e" % (storage, r))
+
+
+def test_re1e4_100_tau051_srt_blows_up_equilibrium_lid(smrt):
+    u = lid_speed(1e4, 0.51, 100)
+    with smrt.Solver(100, 100, scheme="srt", boundary="cavity_eqlid", storage="f32", tau=0.51,
+                     u_lid=u) as s:
+        s.step(5_000)
         with pytest.raises(smrt.UnstableError):
             s.residual()

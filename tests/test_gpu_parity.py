@@ -50,13 +50,13 @@ def test_cavity_64_re100_2000_steps(smrt, scheme, storage):
 
 # --- one step from far-from-equilibrium populations: collision + streaming + walls -------
 
-@pytest.mark.parametrize("boundary", ["periodic", "cavity"])
+@pytest.mark.parametrize("boundary", ["periodic", "cavity", "cavity_eqlid"])
 @pytest.mark.parametrize("scheme,tau,tau_s", [("srt", 0.57, 1.0), ("smrt", 0.57, 1.0),
                                               ("smrt", 1.3, 1.0), ("trt", 0.6, 0.83)])
 @pytest.mark.parametrize("nx,ny", [(3, 3), (37, 29), (300, 70), (64, 256)])
 def test_one_step_from_nonequilibrium_populations(smrt, boundary, scheme, tau, tau_s, nx, ny):
     f0 = inputs.perturbed_populations(nx, ny, eps=0.05, seed=nx * 1000 + ny)
-    u = 0.08 if boundary == "cavity" else 0.0
+    u = 0.08 if boundary.startswith("cavity") else 0.0
     L = oracle_lattice(nx, ny, scheme, boundary, tau, u, tau_s)
     want = L.collide(oracle_from_post_collision(L, np.moveaxis(f0, 0, -1), 1))
     for storage, tol in (("f64", 1e-15), ("f32", 2e-8), ("f32x", 2e-8)):
@@ -68,6 +68,29 @@ def test_one_step_from_nonequilibrium_populations(smrt, boundary, scheme, tau, t
         err = np.max(np.abs(got - want))
         print("one-step %s %s %s %dx%d: %.3e" % (boundary, scheme, storage, nx, ny, err))
         assert err < tol
+
+
+# --- the second lid reading: an equilibrium lid on the top row -----------------------------
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f32x"])
+@pytest.mark.parametrize("scheme", ["smrt", "srt"])
+def test_equilibrium_lid_cavity_64_re100_2000_steps(smrt, scheme, storage):
+    """The 64^2 cavity at Re 100 under the equilibrium-lid reading, against the
+    oracle's equilibrium lid after 2000 steps."""
+    n, u, steps = 64, 0.1, 2000
+    with smrt.Solver(n, n, scheme=scheme, boundary="cavity_eqlid", storage=storage, re=100.0,
+                     u_lid=u) as s:
+        assert s.steps_per_launch == 1
+        with pytest.raises(smrt.SmrtError):
+            s.set_steps_per_launch(2)
+        s.step(steps)
+        g = gpu_fields(s)
+    L = oracle_lattice(n, n, scheme, "cavity_eqlid", 3 * u * n / 100.0 + 0.5, u)
+    o = L.fields(L.run(L.init_equilibrium(), steps))
+    err = max_vel_err(g, o) / u
+    print("cavity64 equilibrium lid %s %s max|du|/U = %.3e" % (scheme, storage, err))
+    assert err <= TOL[storage]
+    assert np.max(np.abs(g[1][-1] - u)) < (1e-14 if storage == "f64" else 1e-7)   # the lid row moves with U
 
 
 # --- multi-step periodic fields with ragged tiles, every scheme -------------------------
