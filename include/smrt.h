@@ -159,6 +159,22 @@ int smrt_residual(smrt_ctx* c, double* out);
  * stream.  SMRT_EUNSTABLE (and *out = NaN) on a non-finite value. */
 int smrt_mass(smrt_ctx* c, double* out);
 
+/* For callers that cannot allocate or synchronize: code under HIP graph
+ * capture, serving loops that forbid allocation, harnesses without hipMalloc.
+ * The mass of smrt_mass, enqueued on the context's stream without a host
+ * round trip: dev_out (device, 2 doubles) receives sum rho in FP64 (the same
+ * kernels and fixed summation order as smrt_mass, so the same value) and the
+ * number of nodes holding a non-finite density or velocity (0 when stable).
+ * Allocates nothing: the partial sums live in a static device array of the
+ * library, 2048 x 4 + 4 doubles (65.6 KB) on each GPU it runs on, kept until
+ * the process ends; its address on a device is taken when the first context
+ * is created on that device.  Every partial is rewritten by each call, so no
+ * clearing is needed; calls that overlap on one GPU (several streams or
+ * host threads) share the array and race.  Asynchronous.  SMRT_EINVAL for
+ * NULL arguments or a reduction wider than the static array (never for
+ * lattices the library accepts); SMRT_EDEVICE if a launch fails. */
+int smrt_mass_noalloc(smrt_ctx* c, double* dev_out);
+
 /* Steps taken since creation or the last state reset. */
 int64_t smrt_steps_done(const smrt_ctx* c);
 

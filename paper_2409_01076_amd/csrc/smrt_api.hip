@@ -16,6 +16,7 @@
 #include <cstring>
 #include <type_traits>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -41,6 +42,23 @@ __global__ void __launch_bounds__(RED_THREADS) reduce_finish(const double* __res
         double t = 0.0;
         for (int w = 0; w < RED_WAVES; ++w) t += lds[threadIdx.x][w];
         out[threadIdx.x] = t;
+    }
+}
+
+// Device scratch of smrt_mass_noalloc: the reduction's per-block partial
+// sums and its four totals, in a file-scope array (one copy per GPU, held
+// until the process ends).  Host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device.
+constexpr int SCRATCH_DOUBLES = 2048 * RED_VALUES + RED_VALUES;
+static __device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+
+// out[0] = nodes + sum (rho - 1) (the mass), out[1] = non-finite nodes, from
+// the four totals of reduce_finish.
+__global__ void mass_from_sums(const double* __restrict__ sums, double nodes, double* __restrict__ out)
+{
+    if (threadIdx.x == 0) {
+        out[0] = nodes + sums[2];
+        out[1] = sums[3];
     }
 }
 
@@ -199,6 +217,7 @@ struct smrt_ctx {
     char* ws = nullptr;
     bool owns_ws = false;
     double* host_result = nullptr; // pinned, RED_VALUES doubles
+    int device = 0;                // HIP device current at creation
     int cur = 0;                   // 0: state in buffer A, 1: in buffer B
     int64_t steps = 0, snap_step = 0;
     int bx = 256, by = 1, rows = 1;
@@ -232,6 +251,31 @@ struct smrt_ctx {
 namespace {
 
 int elementwise_blocks(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 65536); }
+
+// Address of the device scratch array on each GPU, taken once per device
+// (with that device current) by scratch_setup.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch[kMaxDevices] = {};
+
+int scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return fail(SMRT_EINVAL, "device %d out of range", device);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch[device]) return SMRT_OK;
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(smrt::scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch[device] = static_cast<double*>(ptr);
+    return SMRT_OK;
+}
+
+double* scratch_ptr(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    return g_scratch[device];
+}
 
 template <typename T> int launch_step(smrt_ctx* c, const void* src, void* dst)
 {
@@ -585,7 +629,16 @@ int smrt_create(const smrt_params* p, void* dev_ws, size_t ws_bytes, smrt_ctx** 
         } else {
             c->bx = 64; c->by = 4;
         }
-        hipError_t e;
+        hipError_t e = hipGetDevice(&c->device);
+        if (e != hipSuccess) {
+            delete c;
+            return hip_fail(e, "hipGetDevice");
+        }
+        rc = scratch_setup(c->device);
+        if (rc) {
+            delete c;
+            return rc;
+        }
         if (dev_ws) {
             c->ws = static_cast<char*>(dev_ws);
         } else {
@@ -740,6 +793,27 @@ int smrt_mass(smrt_ctx* c, double* out)
     }
     *out = (double)c->nodes() + drho;
     return SMRT_OK;
+}
+
+int smrt_mass_noalloc(smrt_ctx* c, double* dev_out)
+{
+    if (!c || !dev_out) return fail(SMRT_EINVAL, "context or output is NULL");
+    const int nparts = c->L.red_blocks;
+    if ((int64_t)nparts * smrt::RED_VALUES + smrt::RED_VALUES > smrt::SCRATCH_DOUBLES)
+        return fail(SMRT_EINVAL, "%d reduction blocks exceed the %d doubles of device scratch", nparts,
+                    smrt::SCRATCH_DOUBLES);
+    double* scratch = scratch_ptr(c->device);
+    if (!scratch) return fail(SMRT_ESTATE, "device scratch of device %d was not set up", c->device);
+    double* partials = scratch;
+    double* sums = scratch + (int64_t)nparts * smrt::RED_VALUES;
+    const smrt::Geom g = c->geom();
+    with_storage(c, c->buffer(c->cur), [&](auto* s) {
+        smrt::reduce_partials<<<nparts, smrt::RED_THREADS, 0, c->stream>>>(s, g, c->snap_x(), c->snap_y(), 0,
+                                                                           partials);
+    });
+    smrt::reduce_finish<<<1, smrt::RED_THREADS, 0, c->stream>>>(partials, nparts, sums);
+    smrt::mass_from_sums<<<1, 64, 0, c->stream>>>(sums, (double)c->nodes(), dev_out);
+    return after_launch("mass reduction (device scratch)");
 }
 
 int64_t smrt_steps_done(const smrt_ctx* c) { return c ? c->steps : -1; }

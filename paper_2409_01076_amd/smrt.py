@@ -23,7 +23,7 @@ _IO_DTYPES = {torch.float64: 0, torch.float32: 1}
 EXPORTED = (
     "smrt_workspace_bytes", "smrt_create", "smrt_init_fields", "smrt_set_populations",
     "smrt_get_populations", "smrt_step", "smrt_moments", "smrt_residual", "smrt_mass",
-    "smrt_steps_done", "smrt_tau", "smrt_set_launch", "smrt_set_steps_per_launch",
+    "smrt_mass_noalloc", "smrt_steps_done", "smrt_tau", "smrt_set_launch", "smrt_set_steps_per_launch",
     "smrt_get_steps_per_launch", "smrt_set_tile_order",
     "smrt_synchronize", "smrt_destroy",
     "smrt_last_error", "smrt_copy_kernel",
@@ -105,6 +105,7 @@ def load():
         "smrt_moments": (ctypes.c_int, [vp, vp, vp, vp, i32]),
         "smrt_residual": (ctypes.c_int, [vp, dp]),
         "smrt_mass": (ctypes.c_int, [vp, dp]),
+        "smrt_mass_noalloc": (ctypes.c_int, [vp, vp]),
         "smrt_steps_done": (i64, [vp]),
         "smrt_tau": (ctypes.c_double, [vp]),
         "smrt_set_launch": (ctypes.c_int, [vp, i32, i32, i32]),
@@ -329,6 +330,15 @@ class Solver:
         out = ctypes.c_double()
         _check(load().smrt_mass(self._ctx, ctypes.byref(out)))
         return out.value
+
+    def mass_noalloc(self, out):
+        """Enqueues (sum rho, non-finite node count) into a float64 device
+        tensor of 2 elements, without allocation or synchronization."""
+        if out.device != self.device or out.dtype != torch.float64 or out.numel() < 2 or not out.is_contiguous():
+            raise ValueError("expected a contiguous float64 tensor of 2 elements on %s" % self.device)
+        with _caller_order(self.stream, self.device):
+            _check(load().smrt_mass_noalloc(self._ctx, _ptr(out)))
+        return out
 
     def run_to_steady(self, tol=1e-7, window=1000, max_steps=10_000_000, callback=None):
         """Steps in windows of `window` until the windowed residual drops below
