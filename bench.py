@@ -45,6 +45,8 @@ VALU_FILE = os.path.join(ROOT, "profiles", "valu_stream_collide.json")
 # FP32 operation is one such instruction.
 VALU_PEAK_G = 256 * 4 * 2.4 / 4
 STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2, "f32x": 4}
+# moment storage: bytes a node reads and writes per step (3 moments + 2 amplitudes)
+MOMENT_NODE_BYTES = {"m64": 40, "m16": 16, "mbf16": 16}
 
 
 def kernel_source_hash():
@@ -65,10 +67,12 @@ def parse():
     ap.add_argument("--window", type=int, default=1000, help="time steps per residual window")
     ap.add_argument("--n", type=int, default=4096, help="lattice side")
     ap.add_argument("--scheme", default="smrt", choices=["smrt", "srt", "trt"])
-    ap.add_argument("--storage", default=None, choices=["f32", "f64", "f16", "bf16", "f32x"],
+    ap.add_argument("--storage", default=None, choices=["f32", "f64", "f16", "bf16", "f32x", "m64", "m16", "mbf16"],
                     help="stored populations (default: f32x for the cavity workload, whose 1e-5 U bound against FP64 needs FP64 collision arithmetic; f32 otherwise)")
     ap.add_argument("--tau", type=float, default=0.6)
     ap.add_argument("--launch", default="", help="bx,by,rows of the stream-collide kernel")
+    ap.add_argument("--steps-per-launch", type=int, default=0,
+                    help="time steps per kernel launch (0: the library's default for the lattice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget")
     ap.add_argument("--workload", default="tg",
@@ -174,7 +178,7 @@ def pair_rates(n, steps=1000, storages=("f32",)):
     fields = [torch.from_numpy(a).to("cuda:0") for a in inputs.taylor_green(n, n, u0=0.05, noise=1e-3)]
     out = {}
     for storage in storages:
-        for scheme in ("smrt", "srt"):
+        for scheme in (("smrt",) if storage.startswith("m") else ("smrt", "srt")):
             for tau in (0.51, 0.6, 1.0):
                 with smrt.Solver(n, n, scheme=scheme, boundary="periodic", storage=storage, tau=tau) as s:
                     s.init_fields(*fields)
@@ -311,7 +315,8 @@ def cavity_to_steady(args, storage=None, quiet=False):
         first, level = args.schedule.split(":")
         stages.append((first, float(level)))
     stages.append((storage, args.tol))
-    for scheme in ("smrt", "srt"):
+    # moment storage holds the SmrtLBM state only
+    for scheme in (("smrt",) if storage.startswith("m") else ("smrt", "srt")):
         solver = smrt.Solver(n, n, scheme=scheme, boundary="cavity", storage=stages[0][0],
                              re=args.re, u_lid=0.1, device="cuda:0")
         if args.launch:
@@ -381,7 +386,7 @@ def precision_study(args):
     n = args.n if args.n != 4096 else 2048
     U = 0.1
     ref, ref_steady, n_steady, n_ref, out = None, None, None, None, {}
-    storages = ("f64", "f32x", "f32", "f16", "bf16")
+    storages = ("f64", "f32x", "f32", "f16", "bf16") + (("m16", "mbf16") if args.scheme == "smrt" else ())
     for storage in storages:
         s = smrt.Solver(n, n, scheme=args.scheme, boundary="cavity", storage=storage, re=args.re,
                         u_lid=U, device="cuda:0")
@@ -616,6 +621,8 @@ def main():
                          tau=args.tau, tau_s=1.0, device="cuda:0")
     if args.launch:
         solver.set_launch(*[int(v) for v in args.launch.split(",")])
+    if args.steps_per_launch:
+        solver.set_steps_per_launch(args.steps_per_launch)
     solver.init_fields(*dev)
     del dev
     mass0 = solver.mass()
@@ -665,13 +672,14 @@ def main():
     solver.close()
 
     cells = n * n
-    s = STORAGE_BYTES[args.storage]
+    mom = args.storage in MOMENT_NODE_BYTES
     # The dominant kernel reads d(t) and writes d(t + spl) once per node per
     # launch: 9 loads + 9 stores per node whether it advances one time step
     # (stream_collide) or several through LDS (stream_collide_x2 .. _x5).
-    kernel_name = "stream_collide" if spl == 1 else "stream_collide_x%d" % spl
+    kernel_name = "stream_collide_mom" if mom else ("stream_collide" if spl == 1 else "stream_collide_x%d" % spl)
     launch_ms = (window_ms - rem_ms) / q
-    alg_bytes = 18 * s * cells
+    node_bytes = 2 * MOMENT_NODE_BYTES[args.storage] if mom else 18 * STORAGE_BYTES[args.storage]
+    alg_bytes = node_bytes * cells
     achieved = alg_bytes / (launch_ms / 1e3) / 1e9
     mlups = cells * K * args.steps / wall / 1e6
     traffic = traffic_record(cells, kernel_name)
@@ -690,10 +698,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.storage == "f64" else "f32",
+        "dtype": "f64" if args.storage in ("f64", "f32x", "m64") else "f32",
         "data": "synthetic",
         "config": {
-            "workload": "periodic Taylor-Green %dx%d, %s, %s deviation storage, tau=%g, "
+            "workload": "periodic Taylor-Green %dx%d, %s, %s storage, tau=%g, "
                         "step = %d time steps + residual/mass + moments export"
                         % (n, n, args.scheme, args.storage, args.tau, K),
             "nx": n, "ny": n, "scheme": args.scheme, "storage": args.storage, "tau": args.tau,
@@ -710,8 +718,10 @@ def main():
             "time_steps_per_launch": spl,
             "kernel_avg_us": round(launch_ms * 1e3, 2),
             "algorithmic_bytes_per_launch": alg_bytes,
-            "algorithmic_unit": "one node advanced %d time step%s per launch: 9 reads + 9 writes of %d B"
-                                % (spl, "s" * (spl > 1), s),
+            "algorithmic_unit": ("one node advanced one time step: its 5 moments read and written, %d B"
+                                 % node_bytes) if mom else
+                                ("one node advanced %d time step%s per launch: 9 reads + 9 writes of %d B"
+                                 % (spl, "s" * (spl > 1), STORAGE_BYTES[args.storage])),
         },
         "glups_kernel": round(cells / (kernel_ms / 1e3) / 1e9, 2),
         "copy_kernel_gbs": round(copy_ceiling(alg_bytes // 2), 1),
@@ -756,7 +766,7 @@ def main():
         # cold start to the residual (binary32 storage with FP64 arithmetic,
         # the storage that meets 1e-5 U against FP64, and with binary32
         # arithmetic), and learned warm starts against cold starts
-        out["glups_pairs"] = pair_rates(n, storages=("f32", "f32x"))
+        out["glups_pairs"] = pair_rates(n, storages=("f32", "f32x", "m16"))
         import copy
         cav = copy.copy(args)
         cav.n, cav.schedule, cav.launch = 1024, "", ""

@@ -76,19 +76,34 @@ typedef enum smrt_dtype {
     SMRT_F32 = 1,
     SMRT_F16 = 2, /* storage only: IEEE binary16 deviations, FP32 arithmetic */
     SMRT_BF16 = 3,/* storage only: bfloat16 deviations, FP32 arithmetic      */
-    SMRT_F32X = 4 /* storage only: binary32 deviations, FP64 arithmetic: each
+    SMRT_F32X = 4,/* storage only: binary32 deviations, FP64 arithmetic: each
                      collision is computed in FP64 and rounded once per stored
                      value, so the only FP32 error is the storage's own
                      (binary32 collision arithmetic biases the momentum
                      balance of a slowly converging cavity) */
+    /* Moment storage (SmrtLBM only; cavity or periodic; one time step per
+     * launch).  Eq. (SmrtLBM-1) makes the post-collision populations a
+     * function of five numbers per node, f*_a = f^eq_a(rho, u) + (-1)^a g_grp(a)
+     * with g_1 = (1 - 1/tau) C_1 (axis links) and g_2 = (1 - 1/tau) C_2
+     * (diagonal links), so the state is stored as rho - 1, j = rho u and g_1,
+     * g_2, and each step rebuilds the pulled populations from the
+     * neighbours' moments.  The large equilibrium part keeps binary32 (or
+     * FP64) precision and the small amplitudes, which carry the viscous
+     * stress, get their own 16-bit relative precision. */
+    SMRT_M64 = 5,  /* FP64 moments and amplitudes, FP64 arithmetic (40 B a node) */
+    SMRT_M16 = 6,  /* binary32 moments, FP16 amplitudes (scaled by 2^12), FP32
+                      arithmetic: 16 B a node */
+    SMRT_MBF16 = 7 /* binary32 moments, bfloat16 amplitudes, FP32 arithmetic:
+                      16 B a node */
 } smrt_dtype;
 
 typedef struct smrt_params {
     int32_t nx, ny;    /* lattice nodes along x and y, each >= 3             */
     int32_t scheme;    /* smrt_scheme                                        */
     int32_t boundary;  /* smrt_boundary                                      */
-    int32_t storage;   /* smrt_dtype of the stored populations; arithmetic is
-                          FP64 for SMRT_F64 and SMRT_F32X, FP32 otherwise     */
+    int32_t storage;   /* smrt_dtype of the stored state; arithmetic is FP64
+                          for SMRT_F64, SMRT_F32X and SMRT_M64, FP32
+                          otherwise                                          */
     int32_t reserved0; /* must be 0                                          */
     double tau;        /* > 1/2: used as given.  <= 0: derived from re as
                           tau = 3 |u_lid| nx / re + 1/2, i.e.
@@ -115,7 +130,8 @@ size_t smrt_workspace_bytes(const smrt_params* p);
  * NULL.  SMRT_EINVAL: nx or ny < 3, nx * ny > 2^34, a row of more than
  * 2 MiB of stored values (nx > 262,144 for SMRT_F64, 524,288 for SMRT_F32,
  * 1,048,576 for 16-bit storage: the kernels address a tile through 32-bit
- * byte offsets), unknown enum, relaxation time <= 1/2, |u_lid| >= 1/sqrt(3),
+ * byte offsets), unknown enum, moment storage with a scheme other than
+ * SmrtLBM or with SMRT_CAVITY_EQLID, relaxation time <= 1/2, |u_lid| >= 1/sqrt(3),
  * non-zero reserved fields, out == NULL.  SMRT_ENOMEM:
  * ws_bytes too small or the allocation failed.  On error *out is NULL. */
 int smrt_create(const smrt_params* p, void* dev_ws, size_t ws_bytes, smrt_ctx** out);
@@ -129,7 +145,9 @@ int smrt_init_fields(smrt_ctx* c, const void* rho, const void* ux, const void* u
 /* Replaces the state by the post-collision populations f (device,
  * [9][ny][nx], SMRT_F32 or SMRT_F64, full values), e.g. to resume a run;
  * resets the step counter and the residual snapshot.  Values are rounded to
- * the storage type. */
+ * the storage type; moment storage keeps the density, momentum and the two
+ * group sums of f - f^eq (Eq. sigma1-2-0) as g_1, g_2, which is exact for any
+ * SmrtLBM post-collision state. */
 int smrt_set_populations(smrt_ctx* c, const void* f, int32_t dtype);
 
 /* Writes the current post-collision populations f = w + d (device,
@@ -184,6 +202,7 @@ double smrt_tau(const smrt_ctx* c);
 /* Threads per block along x and y, and rows per thread, for the
  * stream-collide kernel (tuning; results do not depend on it).  bx * by must
  * be 64, 128, 256, 512 or 1024 and bx a multiple of 16; rows in 1..8.
+ * Moment storage: the tile, bx = 64 and by * rows = 8 or 16 (default 8).
  * SMRT_EINVAL otherwise. */
 int smrt_set_launch(smrt_ctx* c, int32_t bx, int32_t by, int32_t rows);
 

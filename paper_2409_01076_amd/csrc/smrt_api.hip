@@ -5,6 +5,7 @@
 
 #include "host_util.hpp"
 #include "lbm_kernels.hpp"
+#include "moment_kernels.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -113,17 +114,26 @@ namespace {
 constexpr size_t kAlign = 256;
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Bytes of the buffer's element type (moment storage: of its moment planes).
 size_t elem_bytes(int storage)
 {
     switch (storage) {
-    case SMRT_F64: return 8;
+    case SMRT_F64:
+    case SMRT_M64: return 8;
     case SMRT_F32:
-    case SMRT_F32X: return 4;
+    case SMRT_F32X:
+    case SMRT_M16:
+    case SMRT_MBF16: return 4;
     case SMRT_F16:
     case SMRT_BF16: return 2;
     default: return 0;
     }
 }
+
+bool is_moment(int storage) { return storage == SMRT_M64 || storage == SMRT_M16 || storage == SMRT_MBF16; }
+
+// Bytes of one amplitude of the moment storage.
+size_t amp_bytes(int storage) { return storage == SMRT_M64 ? 8 : 2; }
 
 // Byte offsets of everything the context keeps in its device workspace.
 struct Layout {
@@ -151,7 +161,10 @@ Layout make_layout(int nx, int ny, int storage)
     L.pitch = (int)round_up((size_t)nx, kAlign / e);
     const size_t plane_bytes = round_up((size_t)L.pitch * ny * e, 65536) + plane_pad_bytes();
     L.plane = (int64_t)(plane_bytes / e);
-    L.buffer = 9 * plane_bytes;
+    // populations: 9 planes; moments: 3 planes of the moment type and 2 of
+    // the amplitude type with the same element count
+    L.buffer = is_moment(storage) ? round_up(3 * plane_bytes + 2 * (size_t)L.plane * amp_bytes(storage), kAlign)
+                                  : 9 * plane_bytes;
     const size_t n = (size_t)nx * ny;
     L.red_blocks = (int)std::min<size_t>((n + smrt::RED_THREADS - 1) / smrt::RED_THREADS, 2048);
     size_t off = 0;
@@ -201,6 +214,9 @@ int check_params(const smrt_params* p, double* tau_out)
     }
     if (!(tau > 0.5) || !std::isfinite(tau))
         return fail(SMRT_EINVAL, "relaxation time must exceed 1/2 (got %.17g)", tau);
+    if (is_moment(p->storage) && (p->scheme != SMRT_SCHEME_SMRT || p->boundary == SMRT_CAVITY_EQLID))
+        return fail(SMRT_EINVAL, "moment storage holds the SmrtLBM state only, with the moving-wall cavity or periodic "
+                                 "boundaries");
     if (p->scheme == SMRT_SCHEME_TRT && (!(p->tau_s > 0.5) || !std::isfinite(p->tau_s)))
         return fail(SMRT_EINVAL, "TRT needs tau_s > 1/2 (got %g)", p->tau_s);
     *tau_out = tau;
@@ -224,6 +240,7 @@ struct smrt_ctx {
     int fused = 1;                 // time steps per launch (1, or 2 .. 5 with the LDS-blocked kernels)
     int fused_cols = 64, fused_rows = 8; // tile of the multi-step kernels
     int panel = 0;                 // multi-step kernels: tile order (0 = row-major)
+    int mom_rows = 8;              // moment storage: tile rows (64 x 8 or 64 x 16)
 
     void* buffer(int which) const { return ws + (which == 0 ? L.off_a : L.off_b); }
     double* snap_x() const { return reinterpret_cast<double*>(ws + L.off_snap_x); }
@@ -316,6 +333,38 @@ template <typename T> int launch_step(smrt_ctx* c, const void* src, void* dst)
     default: go(std::integral_constant<int, smrt::TRT>{}); break;
     }
     return SMRT_OK;
+}
+
+// One SmrtLBM step on moment storage: 64 x 8 or 64 x 16 tiles, one node a
+// thread.
+template <typename MS, int TY> int launch_step_mom_tile(smrt_ctx* c, const void* src, void* dst)
+{
+    using C = typename smrt::MomPlanes<MS>::C;
+    constexpr int TX = 64;
+    smrt::Geom g = c->geom();
+    g.tiles_x = (g.nx + TX - 1) / TX;
+    const int64_t blocks = (int64_t)g.tiles_x * ((g.ny + TY - 1) / TY);
+    if (blocks > std::numeric_limits<int>::max()) return fail(SMRT_EINVAL, "grid too large");
+    smrt::Coef<C> k;
+    k.omega = (C)(1.0 / c->tau);
+    k.omega_s = (C)1;
+    k.a = (C)(1.0 - 1.0 / c->tau);
+    k.b = (C)0;
+    k.lid = (C)(c->p.boundary == SMRT_CAVITY ? c->p.u_lid / 6.0 : 0.0);
+    k.ulid = (C)0;
+    const MS* s = static_cast<const MS*>(src);
+    MS* d = static_cast<MS*>(dst);
+    if (c->p.boundary == SMRT_PERIODIC)
+        smrt::stream_collide_mom<MS, smrt::PERIODIC, TX, TY><<<(unsigned)blocks, TX * TY, 0, c->stream>>>(s, d, g, k);
+    else
+        smrt::stream_collide_mom<MS, smrt::CAVITY, TX, TY><<<(unsigned)blocks, TX * TY, 0, c->stream>>>(s, d, g, k);
+    return SMRT_OK;
+}
+
+template <typename MS> int launch_step_mom(smrt_ctx* c, const void* src, void* dst)
+{
+    if (c->mom_rows == 16) return launch_step_mom_tile<MS, 16>(c, src, dst);
+    return launch_step_mom_tile<MS, 8>(c, src, dst);
 }
 
 // Threads per multi-step workgroup.  Four- and five-step tiles of 512 nodes
@@ -447,6 +496,9 @@ int dispatch_multi(smrt_ctx* c, int k, int cols, int rows, const void* src, void
 int dispatch_step(smrt_ctx* c, const void* src, void* dst)
 {
     switch (c->p.storage) {
+    case SMRT_M64: return launch_step_mom<smrt::m64>(c, src, dst);
+    case SMRT_M16: return launch_step_mom<smrt::m16>(c, src, dst);
+    case SMRT_MBF16: return launch_step_mom<smrt::mbf16>(c, src, dst);
     case SMRT_F64: return launch_step<double>(c, src, dst);
     case SMRT_F32: return launch_step<float>(c, src, dst);
     case SMRT_F32X: return launch_step<smrt::f32x>(c, src, dst);
@@ -455,7 +507,26 @@ int dispatch_step(smrt_ctx* c, const void* src, void* dst)
     }
 }
 
-// Calls fn(T*) with the state buffer typed by the storage type.
+// Calls fn(T*) with the state buffer typed by the storage type: population
+// storage only (with_storage), moment storage only (with_moment_storage), or
+// either (with_any_storage, for the kernels that read the moments of a node).
+template <typename Fn> int with_moment_storage(smrt_ctx* c, void* buf, Fn&& fn)
+{
+    switch (c->p.storage) {
+    case SMRT_M64: fn(static_cast<smrt::m64*>(buf)); break;
+    case SMRT_M16: fn(static_cast<smrt::m16*>(buf)); break;
+    default: fn(static_cast<smrt::mbf16*>(buf)); break;
+    }
+    return SMRT_OK;
+}
+
+template <typename Fn> int with_storage(smrt_ctx* c, void* buf, Fn&& fn);
+
+template <typename Fn> int with_any_storage(smrt_ctx* c, void* buf, Fn&& fn)
+{
+    return is_moment(c->p.storage) ? with_moment_storage(c, buf, fn) : with_storage(c, buf, fn);
+}
+
 template <typename Fn> int with_storage(smrt_ctx* c, void* buf, Fn&& fn)
 {
     switch (c->p.storage) {
@@ -481,7 +552,7 @@ int run_reduction(smrt_ctx* c, int update)
 {
     const smrt::Geom g = c->geom();
     void* state = c->buffer(c->cur);
-    with_storage(c, state, [&](auto* s) {
+    with_any_storage(c, state, [&](auto* s) {
         smrt::reduce_partials<<<c->L.red_blocks, smrt::RED_THREADS, 0, c->stream>>>(
             s, g, c->snap_x(), c->snap_y(), update, c->partials());
     });
@@ -498,7 +569,7 @@ int run_reduction(smrt_ctx* c, int update)
 int refresh_snapshot(smrt_ctx* c)
 {
     const smrt::Geom g = c->geom();
-    with_storage(c, c->buffer(c->cur), [&](auto* s) {
+    with_any_storage(c, c->buffer(c->cur), [&](auto* s) {
         smrt::reduce_partials<<<c->L.red_blocks, smrt::RED_THREADS, 0, c->stream>>>(
             s, g, c->snap_x(), c->snap_y(), 1, c->partials());
     });
@@ -510,10 +581,16 @@ int refresh_snapshot(smrt_ctx* c)
 template <typename F> int init_fields_typed(smrt_ctx* c, const void* rho, const void* ux, const void* uy)
 {
     const smrt::Geom g = c->geom();
-    with_storage(c, c->buffer(c->cur), [&](auto* s) {
-        smrt::init_equilibrium<<<elementwise_blocks(c->nodes()), 256, 0, c->stream>>>(
-            s, g, static_cast<const F*>(rho), static_cast<const F*>(ux), static_cast<const F*>(uy));
-    });
+    if (is_moment(c->p.storage))
+        with_moment_storage(c, c->buffer(c->cur), [&](auto* s) {
+            smrt::init_moments<<<elementwise_blocks(c->nodes()), 256, 0, c->stream>>>(
+                s, g, static_cast<const F*>(rho), static_cast<const F*>(ux), static_cast<const F*>(uy));
+        });
+    else
+        with_storage(c, c->buffer(c->cur), [&](auto* s) {
+            smrt::init_equilibrium<<<elementwise_blocks(c->nodes()), 256, 0, c->stream>>>(
+                s, g, static_cast<const F*>(rho), static_cast<const F*>(ux), static_cast<const F*>(uy));
+        });
     return after_launch("init_equilibrium");
 }
 
@@ -619,7 +696,7 @@ int smrt_create(const smrt_params* p, void* dev_ws, size_t ws_bytes, smrt_ctx** 
                 if (fits(2, c->fused_rows)) c->fused = 2;
             }
         }
-        if (p->boundary == SMRT_CAVITY_EQLID) c->fused = 1; // one-step kernel only
+        if (p->boundary == SMRT_CAVITY_EQLID || is_moment(p->storage)) c->fused = 1; // one-step kernels only
         if (p->nx >= 512) {
             c->bx = 512; c->by = 1;
         } else if (p->nx >= 256) {
@@ -686,12 +763,20 @@ int smrt_set_populations(smrt_ctx* c, const void* f, int32_t dtype)
     if (rc) return rc;
     const smrt::Geom g = c->geom();
     const int blocks = elementwise_blocks(c->nodes());
-    with_storage(c, c->buffer(c->cur), [&](auto* s) {
-        if (dtype == SMRT_F64)
-            smrt::set_populations<<<blocks, 256, 0, c->stream>>>(s, g, static_cast<const double*>(f));
-        else
-            smrt::set_populations<<<blocks, 256, 0, c->stream>>>(s, g, static_cast<const float*>(f));
-    });
+    if (is_moment(c->p.storage))
+        with_moment_storage(c, c->buffer(c->cur), [&](auto* s) {
+            if (dtype == SMRT_F64)
+                smrt::set_populations_mom<<<blocks, 256, 0, c->stream>>>(s, g, static_cast<const double*>(f));
+            else
+                smrt::set_populations_mom<<<blocks, 256, 0, c->stream>>>(s, g, static_cast<const float*>(f));
+        });
+    else
+        with_storage(c, c->buffer(c->cur), [&](auto* s) {
+            if (dtype == SMRT_F64)
+                smrt::set_populations<<<blocks, 256, 0, c->stream>>>(s, g, static_cast<const double*>(f));
+            else
+                smrt::set_populations<<<blocks, 256, 0, c->stream>>>(s, g, static_cast<const float*>(f));
+        });
     rc = after_launch("set_populations");
     if (rc) return rc;
     return refresh_snapshot(c);
@@ -705,12 +790,20 @@ int smrt_get_populations(smrt_ctx* c, void* f, int32_t dtype)
     if (rc) return rc;
     const smrt::Geom g = c->geom();
     const int blocks = elementwise_blocks(c->nodes());
-    with_storage(c, c->buffer(c->cur), [&](auto* s) {
-        if (dtype == SMRT_F64)
-            smrt::get_populations<<<blocks, 256, 0, c->stream>>>(s, g, static_cast<double*>(f));
-        else
-            smrt::get_populations<<<blocks, 256, 0, c->stream>>>(s, g, static_cast<float*>(f));
-    });
+    if (is_moment(c->p.storage))
+        with_moment_storage(c, c->buffer(c->cur), [&](auto* s) {
+            if (dtype == SMRT_F64)
+                smrt::get_populations_mom<<<blocks, 256, 0, c->stream>>>(s, g, static_cast<double*>(f));
+            else
+                smrt::get_populations_mom<<<blocks, 256, 0, c->stream>>>(s, g, static_cast<float*>(f));
+        });
+    else
+        with_storage(c, c->buffer(c->cur), [&](auto* s) {
+            if (dtype == SMRT_F64)
+                smrt::get_populations<<<blocks, 256, 0, c->stream>>>(s, g, static_cast<double*>(f));
+            else
+                smrt::get_populations<<<blocks, 256, 0, c->stream>>>(s, g, static_cast<float*>(f));
+        });
     return after_launch("get_populations");
 }
 
@@ -750,7 +843,7 @@ int smrt_moments(smrt_ctx* c, void* rho, void* ux, void* uy, int32_t dtype)
     if (!rho && !ux && !uy) return SMRT_OK;
     const smrt::Geom g = c->geom();
     const int blocks = elementwise_blocks(c->nodes());
-    with_storage(c, c->buffer(c->cur), [&](auto* s) {
+    with_any_storage(c, c->buffer(c->cur), [&](auto* s) {
         if (dtype == SMRT_F64)
             smrt::export_moments<<<blocks, 256, 0, c->stream>>>(s, g, static_cast<double*>(rho),
                                                                 static_cast<double*>(ux), static_cast<double*>(uy));
@@ -807,7 +900,7 @@ int smrt_mass_noalloc(smrt_ctx* c, double* dev_out)
     double* partials = scratch;
     double* sums = scratch + (int64_t)nparts * smrt::RED_VALUES;
     const smrt::Geom g = c->geom();
-    with_storage(c, c->buffer(c->cur), [&](auto* s) {
+    with_any_storage(c, c->buffer(c->cur), [&](auto* s) {
         smrt::reduce_partials<<<nparts, smrt::RED_THREADS, 0, c->stream>>>(s, g, c->snap_x(), c->snap_y(), 0,
                                                                            partials);
     });
@@ -823,6 +916,12 @@ double smrt_tau(const smrt_ctx* c) { return c ? c->tau : std::numeric_limits<dou
 int smrt_set_launch(smrt_ctx* c, int32_t bx, int32_t by, int32_t rows)
 {
     if (!c) return fail(SMRT_EINVAL, "context is NULL");
+    if (is_moment(c->p.storage)) {
+        if (bx != 64 || (int64_t)by * rows != 8 && (int64_t)by * rows != 16)
+            return fail(SMRT_EINVAL, "moment storage takes 64 x 8 or 64 x 16 tiles (got %d x %d x %d)", bx, by, rows);
+        c->mom_rows = by * rows;
+        return SMRT_OK;
+    }
     const int64_t threads = (int64_t)bx * by;
     if (bx < 16 || bx % 16 || by < 1 || (threads != 64 && threads != 128 && threads != 256 && threads != 512 &&
                                           threads != 1024))
@@ -840,6 +939,8 @@ int smrt_set_steps_per_launch(smrt_ctx* c, int32_t steps, int32_t tile_cols, int
     if (steps < 1 || steps > 5) return fail(SMRT_EINVAL, "steps per launch must be 1 .. 5 (got %d)", steps);
     if (steps > 1 && c->p.boundary == SMRT_CAVITY_EQLID)
         return fail(SMRT_EINVAL, "the equilibrium lid runs one time step per launch");
+    if (steps > 1 && is_moment(c->p.storage))
+        return fail(SMRT_EINVAL, "moment storage runs one time step per launch");
     if (steps == 1) { // one step per launch has no tile: keep the multi-step one
         c->fused = 1;
         return SMRT_OK;

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libsmrt.so")
 OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
 SCHEMES = {"srt": 0, "smrt": 1, "trt": 2}
 BOUNDARIES = {"cavity": 0, "periodic": 1, "cavity_eqlid": 2}
-STORAGE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3, "f32x": 4}
+STORAGE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3, "f32x": 4, "m64": 5, "m16": 6, "mbf16": 7}
 _IO_DTYPES = {torch.float64: 0, torch.float32: 1}
 
 EXPORTED = (
@@ -200,8 +200,9 @@ class Solver:
     ``boundary`` in {'cavity', 'periodic', 'cavity_eqlid'} ('cavity_eqlid': the
     cavity with the equilibrium lid on its top row, one step per launch),
     ``storage`` in {'f64', 'f32',
-    'f16', 'bf16', 'f32x'} ('f32x': FP32 storage with FP64 collision
-    arithmetic); give ``tau`` directly or ``re`` (then tau = 3 U N / Re + 1/2).
+    'f16', 'bf16', 'f32x', 'm64', 'm16', 'mbf16'} ('f32x': FP32 storage with
+    FP64 collision arithmetic; 'm*': SmrtLBM moment storage, binary32 (FP64)
+    density and momentum with 16-bit (FP64) non-equilibrium amplitudes); give ``tau`` directly or ``re`` (then tau = 3 U N / Re + 1/2).
     The workspace is a torch uint8 tensor on ``device``; work goes to the
     current torch stream of that device at construction time.  Calls that take
     or return tensors are ordered against the caller's current stream, so the

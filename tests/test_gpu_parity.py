@@ -93,6 +93,95 @@ def test_equilibrium_lid_cavity_64_re100_2000_steps(smrt, scheme, storage):
     assert np.max(np.abs(g[1][-1] - u)) < (1e-14 if storage == "f64" else 1e-7)   # the lid row moves with U
 
 
+# --- moment storage: the SmrtLBM state as (rho - 1, j, (1 - 1/tau) C_1, (1 - 1/tau) C_2) --------
+
+def project_smrt(f, tau):
+    """Test-side projection of full populations (ny, nx, 9) onto the
+    five-number SmrtLBM form: the moments, and the group sums of f - f^eq
+    (Eq. sigma1-2-0) as the amplitudes of the axis and diagonal links."""
+    ex, ey, w, _ = O.constants()
+    rho = f.sum(axis=-1)
+    ux, uy = (f * ex).sum(axis=-1) / rho, (f * ey).sum(axis=-1) / rho
+    feq = np.empty_like(f)
+    for (j, i) in np.ndindex(rho.shape):
+        feq[j, i] = O.equilibrium(rho[j, i], ux[j, i], uy[j, i])
+    sgn = np.array([0, -1, 1, -1, 1, -1, 1, -1, 1])
+    dev = (f - feq) * sgn
+    g1, g2 = dev[..., 1:5].sum(axis=-1) / 4, dev[..., 5:9].sum(axis=-1) / 4
+    amp = np.where(np.arange(9) < 5, g1[..., None], g2[..., None]) * sgn
+    return feq + amp
+
+
+@pytest.mark.parametrize("boundary", ["cavity", "periodic"])
+@pytest.mark.parametrize("nx,ny", [(3, 3), (37, 29), (300, 70)])
+def test_moment_storage_one_step_fp64(smrt, boundary, nx, ny):
+    """One step from far-from-equilibrium populations projected onto the
+    SmrtLBM form, FP64 moment storage: the stored state equals the projection,
+    and one step equals the oracle's collide(stream(.)) element by element."""
+    f0 = np.moveaxis(inputs.perturbed_populations(nx, ny, eps=0.05, seed=nx * 7 + ny), 0, -1)
+    tau, u = 0.57, (0.08 if boundary == "cavity" else 0.0)
+    fp = project_smrt(f0, tau)
+    L = oracle_lattice(nx, ny, "smrt", boundary, tau, u)
+    want = L.collide(oracle_from_post_collision(L, fp, 1))
+    with smrt.Solver(nx, ny, scheme="smrt", boundary=boundary, storage="m64", tau=tau, u_lid=u) as s:
+        s.set_populations(to_dev(np.moveaxis(f0, -1, 0), torch.float64))
+        assert np.max(np.abs(gpu_populations(s) - fp)) < 1e-15
+        s.step(1)
+        got = gpu_populations(s)
+    err = np.max(np.abs(got - want))
+    print("moment storage one step %s %dx%d: %.3e" % (boundary, nx, ny, err))
+    assert err < 1e-15
+
+
+@pytest.mark.parametrize("storage,tol", [("m64", 1e-11), ("m16", 2e-3), ("mbf16", 2e-3)])
+def test_moment_storage_cavity_64_re100(smrt, storage, tol):
+    """The 64^2 cavity at Re 100 after 2000 steps against the oracle: the
+    FP64 moment storage at round-off (it is an exact rewrite of the SmrtLBM
+    state), the 16-bit amplitudes at their own precision."""
+    n, u, steps = 64, 0.1, 2000
+    with smrt.Solver(n, n, scheme="smrt", boundary="cavity", storage=storage, re=100.0, u_lid=u) as s:
+        assert s.steps_per_launch == 1
+        s.step(steps)
+        g = gpu_fields(s)
+        mass = s.mass()
+    L = O.Lattice(n, n, "smrt", re=100.0, u_lid=u)
+    o = L.fields(L.run(L.init_equilibrium(), steps))
+    err = max_vel_err(g, o) / u
+    print("cavity64 moment storage %s: max|du|/U = %.3e, mass drift %.1e" % (storage, err, mass / n / n - 1))
+    assert err <= tol
+    assert abs(mass / n / n - 1) < (1e-13 if storage == "m64" else 1e-7)
+
+
+@pytest.mark.parametrize("storage,tol", [("m64", 1e-11), ("m16", 2e-3), ("mbf16", 2e-3)])
+@pytest.mark.parametrize("tau", [0.51, 0.6, 1.0])
+def test_moment_storage_periodic_taylor_green(smrt, storage, tol, tau):
+    nx, ny, steps, u0 = 300, 157, 300, 0.05
+    rho, ux, uy = inputs.taylor_green(nx, ny, u0=u0, noise=1e-3, seed=11)
+    L = oracle_lattice(nx, ny, "smrt", "periodic", tau)
+    o = L.fields(oracle_from_fields(L, rho, ux, uy, steps))
+    with smrt.Solver(nx, ny, scheme="smrt", boundary="periodic", storage=storage, tau=tau) as s:
+        s.init_fields(to_dev(rho), to_dev(ux), to_dev(uy))
+        s.step(steps)
+        g = gpu_fields(s)
+    err = max_vel_err(g, o) / u0
+    print("tg moment storage %s tau=%g: %.3e of u0" % (storage, tau, err))
+    assert err <= tol
+
+
+def test_moment_storage_rejects_what_it_cannot_hold(smrt):
+    for kw in (dict(scheme="srt"), dict(scheme="trt", tau_s=0.8), dict(boundary="cavity_eqlid")):
+        with pytest.raises(smrt.SmrtError):
+            smrt.Solver(32, 32, storage="m16", tau=0.7, u_lid=0.1, **{"scheme": "smrt", **kw})
+    with smrt.Solver(32, 32, scheme="smrt", storage="m16", tau=0.7, u_lid=0.1) as s:
+        with pytest.raises(smrt.SmrtError):
+            s.set_steps_per_launch(2)
+        s.step(10)
+        a = s.populations(torch.float64)
+    with smrt.Solver(32, 32, scheme="smrt", storage="m16", tau=0.7, u_lid=0.1) as s:
+        s.step(10)
+        assert torch.equal(a, s.populations(torch.float64))      # deterministic
+
+
 # --- multi-step periodic fields with ragged tiles, every scheme -------------------------
 
 @pytest.mark.parametrize("scheme", ["srt", "smrt", "trt"])

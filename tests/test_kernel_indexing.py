@@ -266,3 +266,60 @@ def test_tile_order_visits_every_tile_once(tiles_x, tiles_y, P):
     tx, ty = panel_tile(pos, tiles_x, tiles_y, min(P, tiles_x))
     assert ((tx >= 0) & (tx < tiles_x) & (ty >= 0) & (ty < tiles_y)).all()
     assert len(set(zip(tx.tolist(), ty.tolist()))) == n
+
+
+# --- moment storage (stream_collide_mom, paper_2409_01076_amd/csrc/moment_kernels.hpp) -----
+
+MOM_TX = 64
+
+
+@pytest.mark.parametrize("mom_ty", [8, 16])
+@pytest.mark.parametrize("e_moment,e_amp", [(8, 8), (4, 2)])
+@pytest.mark.parametrize("boundary", ["cavity", "periodic"])
+@pytest.mark.parametrize("nx,ny", [(3, 3), (5, 70), (65, 9), (64, 8), (129, 17), (300, 157)])
+def test_moment_kernel_indexing(mom_ty, e_moment, e_amp, boundary, nx, ny):
+    MOM_TY = mom_ty
+    """Every workgroup of the moment-storage launch: the LDS cells a node reads
+    were staged by the same workgroup, with the value of the node its pull
+    names (wrapped for a periodic lattice); every global access lies in its
+    plane (three moment planes, then two amplitude planes of the same element
+    count, as smrt_api.hip lays them out)."""
+    pitch, plane = layout(nx, ny, e_moment)
+    buffer_bytes = -(-(3 * plane * e_moment + 2 * plane * e_amp) // 256) * 256
+    fx, fy = MOM_TX + 2, MOM_TY + 2
+    tiles_x = -(-nx // MOM_TX)
+    tiles = tiles_x * -(-ny // MOM_TY)
+    per = boundary == "periodic"
+    for tile in range(tiles):
+        x0, y0 = (tile % tiles_x) * MOM_TX, (tile // tiles_x) * MOM_TY
+        staged = {}
+        for i in range(fx * fy):
+            lx, ly = i % fx, i // fx
+            x, y = x0 - 1 + lx, y0 - 1 + ly
+            if per:   # the kernel's wrap: once, then a remainder if still outside
+                x = x + nx if x < 0 else (x - nx if x >= nx else x)
+                y = y + ny if y < 0 else (y - ny if y >= ny else y)
+                x, y = (x if 0 <= x < nx else x % nx), (y if 0 <= y < ny else y % ny)
+            elif not (0 <= x < nx and 0 <= y < ny):
+                continue
+            off = y * pitch + x
+            assert 0 <= off < plane
+            for k in range(3):   # moment planes
+                assert 0 <= (k * plane + off) * e_moment < 3 * plane * e_moment
+            for k in range(2):   # amplitude planes after them
+                b = 3 * plane * e_moment + (k * plane + off) * e_amp
+                assert 3 * plane * e_moment <= b and b + e_amp <= buffer_bytes
+            staged[(lx, ly)] = (x, y)
+        for t in range(MOM_TX * MOM_TY):
+            lx, ly = t % MOM_TX + 1, t // MOM_TX + 1
+            x, y = x0 + lx - 1, y0 + ly - 1
+            if x >= nx or y >= ny:
+                continue
+            assert staged[(lx, ly)] == (x, y)
+            edge = not per and (x in (0, nx - 1) or y in (0, ny - 1))
+            for a in range(1, 9):
+                sx, sy = x - EX[a], y - EY[a]
+                if not edge or (0 <= sx < nx and 0 <= sy < ny):
+                    cell = (lx - EX[a], ly - EY[a])
+                    assert 0 <= cell[0] < fx and 0 <= cell[1] < fy
+                    assert staged[cell] == ((sx % nx, sy % ny) if per else (sx, sy))
