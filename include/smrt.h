@@ -367,7 +367,11 @@ void smrt_batch_destroy(smrt_batch* b);
  * cos(2 pi B p)] with the caller's fixed frequency matrix B (fourier x 3);
  * then (layers - 1) SiLU layers of `width` and a linear output layer.
  * Arithmetic: bfloat16 operands on the matrix cores with FP32 accumulation;
- * FP32 master weights, biases, pre-activations and Adam state.
+ * FP32 master weights, biases, pre-activations (recomputed in the backward
+ * pass, not stored) and Adam state; bfloat16 activations.  Gradients over
+ * the n rows: FP32 sums over blocks of at least 256 rows (at most 256 blocks),
+ * then the blocks summed in a fixed order (results do not depend on
+ * scheduling).
  *
  * Parameter layout (FP32, dense, what set/get_params and smrt_mlp_gradient
  * use): for each layer l in order, W_l as [in_l][out_l] row-major, then b_l
@@ -391,7 +395,8 @@ typedef struct smrt_mlp smrt_mlp;
 /* Number of FP32 parameters in the dense layout (0 if params are invalid). */
 size_t smrt_mlp_param_count(const smrt_mlp_params* p);
 
-/* Device workspace bytes (weights, Adam state, activations of max_batch rows). */
+/* Device workspace bytes (weights, Adam state, activations of max_batch
+ * rows, gradient partials). */
 size_t smrt_mlp_workspace_bytes(const smrt_mlp_params* p);
 
 /* Creates a network (dev_ws as for smrt_create).  Parameters must be set

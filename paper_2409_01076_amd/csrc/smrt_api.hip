@@ -917,7 +917,7 @@ int smrt_set_launch(smrt_ctx* c, int32_t bx, int32_t by, int32_t rows)
 {
     if (!c) return fail(SMRT_EINVAL, "context is NULL");
     if (is_moment(c->p.storage)) {
-        if (bx != 64 || (int64_t)by * rows != 8 && (int64_t)by * rows != 16)
+        if (bx != 64 || ((int64_t)by * rows != 8 && (int64_t)by * rows != 16))
             return fail(SMRT_EINVAL, "moment storage takes 64 x 8 or 64 x 16 tiles (got %d x %d x %d)", bx, by, rows);
         c->mom_rows = by * rows;
         return SMRT_OK;

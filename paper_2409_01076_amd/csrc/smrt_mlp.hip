@@ -3,8 +3,9 @@
 //
 // Network: features [x, y, s, sin(2 pi B p), cos(2 pi B p)] -> (layers - 1)
 // SiLU layers of `width` -> linear layer of `outputs`.  Compute: bf16
-// operands on MFMA with FP32 accumulation; FP32 master weights, biases,
-// pre-activations and Adam state.
+// operands on MFMA with FP32 accumulation; FP32 master weights, biases and
+// Adam state.  Pre-activations are not stored: the backward pass recomputes
+// them (bitwise) from the stored bf16 activations.
 #include "smrt.h"
 
 #include "host_util.hpp"
@@ -24,7 +25,14 @@ using smrt_host::hip_fail;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kReduceRows = 64; // rows summed per chunk in a column-sum pass
+constexpr int kMinSplitRows = 256;           // rows per weight-gradient row block, at least
+constexpr size_t kPartialBytes = 512u << 20; // budget of the row-block partials
+// Workgroups of a forward and of an input-gradient layer, each looping over
+// row tiles with the next tile's rows in flight.  At 65,536 rows a training
+// step measured the same with 512, 768 and 1024 forward groups and slower
+// with 256; 512 input-gradient groups (two a CU, by their LDS) beat 256 and 1024.
+constexpr int kForwardGroups = 512;
+constexpr int kBackwardGroups = 512;
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct MlpLayout {
@@ -33,12 +41,13 @@ struct MlpLayout {
     std::vector<int> in, out, in_real, out_real; // padded and real sizes per layer
     std::vector<size_t> w_off, b_off;             // offsets (floats) in the padded parameter block
     size_t padded_params = 0, real_params = 0;
-    int max_splits = 512;
+    int max_splits = 256;
+    smrt::mlp::LayerTable table;
     // byte offsets in the workspace
-    size_t off_params = 0, off_wbf = 0, off_grad = 0, off_m = 0, off_v = 0, off_fourier = 0, off_x0 = 0,
-           off_z = 0, off_a = 0, off_y = 0, off_dy = 0, off_dz0 = 0, off_dz1 = 0, off_wpart = 0,
-           off_red0 = 0, off_red1 = 0, off_loss = 0, total = 0;
-    size_t z_stride = 0, a_stride = 0; // elements between hidden layers' Z / A arrays
+    size_t off_params = 0, off_wbf = 0, off_wbf_t = 0, off_grad = 0, off_m = 0, off_v = 0, off_fourier = 0,
+           off_x0 = 0, off_a = 0, off_y = 0, off_dy = 0, off_dz0 = 0, off_dz1 = 0, off_wpart = 0, off_loss = 0,
+           total = 0;
+    size_t a_stride = 0; // elements between hidden layers' activation arrays
     int loss_blocks = 0;
 };
 
@@ -49,7 +58,8 @@ int make_layout(const smrt_mlp_params* p, MlpLayout* out)
     if (p->fourier < 0 || p->fourier > 64) return fail(SMRT_EINVAL, "fourier features must be in 0..64");
     if (p->width < 64 || p->width % 64 || p->width > 1024)
         return fail(SMRT_EINVAL, "width must be a multiple of 64 in 64..1024 (got %d)", p->width);
-    if (p->layers < 2 || p->layers > 16) return fail(SMRT_EINVAL, "layers must be in 2..16 (got %d)", p->layers);
+    if (p->layers < 2 || p->layers > smrt::mlp::kMaxLayers)
+        return fail(SMRT_EINVAL, "layers must be in 2..%d (got %d)", smrt::mlp::kMaxLayers, p->layers);
     if (p->outputs < 1 || p->outputs > 64) return fail(SMRT_EINVAL, "outputs must be in 1..64");
     if (p->max_batch < 64 || p->max_batch % 64 || p->max_batch > (1 << 24))
         return fail(SMRT_EINVAL, "max_batch must be a positive multiple of 64 up to 2^24 (got %d)", p->max_batch);
@@ -63,6 +73,7 @@ int make_layout(const smrt_mlp_params* p, MlpLayout* out)
     L.max_batch = p->max_batch;
     L.k0_real = 3 + 2 * p->fourier;
     L.k0 = (int)round_up((size_t)L.k0_real, 64);
+    if (L.k0 > smrt::mlp::kMaxFeatureWidth) return fail(SMRT_EINVAL, "too many input features (%d)", L.k0);
     L.n_last = 64;
     for (int l = 0; l < L.layers; ++l) {
         L.in.push_back(l == 0 ? L.k0 : L.width);
@@ -70,22 +81,26 @@ int make_layout(const smrt_mlp_params* p, MlpLayout* out)
         L.out.push_back(l == L.layers - 1 ? L.n_last : L.width);
         L.out_real.push_back(l == L.layers - 1 ? L.outputs : L.width);
     }
-    size_t pp = 0, rp = 0, max_w = 0, max_wb = 0;
+    size_t pp = 0, rp = 0;
+    L.table.layers = L.layers;
     for (int l = 0; l < L.layers; ++l) {
         L.w_off.push_back(pp);
+        L.table.off[l] = (int64_t)pp;
+        L.table.in[l] = L.in[l];
+        L.table.out[l] = L.out[l];
         pp += (size_t)L.in[l] * L.out[l];
         L.b_off.push_back(pp);
         pp += L.out[l];
         rp += (size_t)L.in_real[l] * L.out_real[l] + L.out_real[l];
-        max_w = std::max(max_w, (size_t)L.in[l] * L.out[l]);
-        max_wb = std::max(max_wb, (size_t)L.in[l] * L.out[l] + L.out[l]);
     }
+    L.table.off[L.layers] = (int64_t)pp;
     L.padded_params = pp;
     L.real_params = rp;
+    // every layer's row-block partials are kept until one pass sums them all
+    while (L.max_splits > 1 && (size_t)L.max_splits * pp * 4 > kPartialBytes) L.max_splits >>= 1;
     const size_t mb = (size_t)L.max_batch;
-    L.loss_blocks = 1024;
+    L.loss_blocks = kForwardGroups;
     const int hidden = L.layers - 1;
-    L.z_stride = mb * L.width;
     L.a_stride = mb * L.width;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -95,24 +110,20 @@ int make_layout(const smrt_mlp_params* p, MlpLayout* out)
     };
     L.off_params = take(pp * 4);
     L.off_wbf = take(pp * 2);
+    L.off_wbf_t = take(pp * 2);
     L.off_grad = take(pp * 4);
     L.off_m = take(pp * 4);
     L.off_v = take(pp * 4);
     L.off_fourier = take((size_t)std::max(1, L.nf) * 3 * 4);
     L.off_x0 = take(mb * L.k0 * 2);
-    L.off_z = take((size_t)hidden * L.z_stride * 4);
     L.off_a = take((size_t)hidden * L.a_stride * 2);
     L.off_y = take(mb * L.outputs * 4);
     L.off_dy = take(mb * L.n_last * 2);
     L.off_dz0 = take(mb * L.width * 2);
     L.off_dz1 = take(mb * L.width * 2);
-    // per split: the weight-gradient partial (in x out) and the bias-gradient
-    // partial (out) after it, the layout of a layer's W and b in the parameters
-    L.off_wpart = take((size_t)L.max_splits * max_wb * 4);
-    // column-sum passes: chunk sums of the split partials
-    const size_t red = (size_t)(L.max_splits + kReduceRows - 1) / kReduceRows * max_wb;
-    L.off_red0 = take(red * 4);
-    L.off_red1 = take(red * 4);
+    // per layer and row block: the weight-gradient partial (in x out) and the
+    // bias-gradient partial (out) after it, laid out as the layer's W and b
+    L.off_wpart = take((size_t)L.max_splits * pp * 4);
     L.off_loss = take((size_t)L.loss_blocks * 8);
     L.total = off;
     *out = std::move(L);
@@ -127,23 +138,23 @@ struct smrt_mlp {
     char* ws = nullptr;
     bool owns_ws = false;
     int64_t adam_steps = 0;
+    int loss_parts = 0; // squared-error partials written by the last forward pass with a target
     bool has_params = false;
     std::vector<double> loss_host;
 
     float* params() const { return reinterpret_cast<float*>(ws + L.off_params); }
     uint16_t* wbf() const { return reinterpret_cast<uint16_t*>(ws + L.off_wbf); }
+    uint16_t* wbf_t() const { return reinterpret_cast<uint16_t*>(ws + L.off_wbf_t); }
     float* grad() const { return reinterpret_cast<float*>(ws + L.off_grad); }
     float* adam_m() const { return reinterpret_cast<float*>(ws + L.off_m); }
     float* adam_v() const { return reinterpret_cast<float*>(ws + L.off_v); }
     float* fourier() const { return reinterpret_cast<float*>(ws + L.off_fourier); }
     uint16_t* x0() const { return reinterpret_cast<uint16_t*>(ws + L.off_x0); }
-    float* z(int l) const { return reinterpret_cast<float*>(ws + L.off_z) + (size_t)l * L.z_stride; }
     uint16_t* a(int l) const { return reinterpret_cast<uint16_t*>(ws + L.off_a) + (size_t)l * L.a_stride; }
     float* y() const { return reinterpret_cast<float*>(ws + L.off_y); }
     uint16_t* dy() const { return reinterpret_cast<uint16_t*>(ws + L.off_dy); }
     uint16_t* dz(int i) const { return reinterpret_cast<uint16_t*>(ws + (i ? L.off_dz1 : L.off_dz0)); }
     float* wpart() const { return reinterpret_cast<float*>(ws + L.off_wpart); }
-    float* red(int i) const { return reinterpret_cast<float*>(ws + (i ? L.off_red1 : L.off_red0)); }
     double* loss_part() const { return reinterpret_cast<double*>(ws + L.off_loss); }
 };
 
@@ -151,14 +162,10 @@ namespace {
 
 int blocks_for(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 65536); }
 
-// C (+ split offset) = opA x opB through the MFMA kernel, or with one split
-// one of the fused epilogues (forward: opA, opB not transposed; input
-// gradient: opB transposed).
+// C (+ split offset) = opA x opB through the general MFMA product kernel.
 int gemm(hipStream_t s, bool ta, bool tb, const uint16_t* A, const uint16_t* B, float* C, int M, int N, int K,
-         int lda, int ldb, int ldc, int splits, int epi = smrt::mlp::EPI_STORE, smrt::mlp::Epilogue ep = {},
-         int64_t split_stride = -1)
+         int lda, int ldb, int ldc, int splits)
 {
-    if (split_stride < 0) split_stride = (int64_t)M * ldc;
     if (M % smrt::mlp::TM || N % smrt::mlp::TN || K % (smrt::mlp::TK * splits))
         return fail(SMRT_EINVAL, "gemm shape %d x %d x %d (splits %d) not tile-aligned", M, N, K, splits);
     // operand slices are staged 8 elements (16 bytes) at a time
@@ -167,26 +174,13 @@ int gemm(hipStream_t s, bool ta, bool tb, const uint16_t* A, const uint16_t* B, 
                                  "(lda %d, ldb %d)", lda, ldb);
     dim3 grid(N / smrt::mlp::TN, M / smrt::mlp::TM, splits);
     const int ks = K / splits;
+    const int64_t ss = (int64_t)M * ldc;
     using namespace smrt::mlp;
     constexpr int T = GEMM_THREADS;
-    const int64_t ss = split_stride;
-    if (epi == EPI_STORE_DB) {
-        if (!ta || tb) return fail(SMRT_EINVAL, "bias-gradient sums need opA transposed and opB not");
-        gemm_bf16<true, false, EPI_STORE_DB><<<grid, T, 0, s>>>(A, B, C, M, N, lda, ldb, ldc, ks, ss, ep);
-        return after_launch("gemm_bf16");
-    }
-    if (epi != EPI_STORE) {
-        if (splits != 1 || ta || tb != (epi == EPI_SILU_GRAD))
-            return fail(SMRT_EINVAL, "fused epilogue %d needs one split and its own transposition", epi);
-        if (epi == EPI_BIAS_SILU) gemm_bf16<false, false, EPI_BIAS_SILU><<<grid, T, 0, s>>>(A, B, C, M, N, lda, ldb, ldc, ks, ss, ep);
-        else if (epi == EPI_BIAS_OUT) gemm_bf16<false, false, EPI_BIAS_OUT><<<grid, T, 0, s>>>(A, B, C, M, N, lda, ldb, ldc, ks, ss, ep);
-        else gemm_bf16<false, true, EPI_SILU_GRAD><<<grid, T, 0, s>>>(A, B, C, M, N, lda, ldb, ldc, ks, ss, ep);
-        return after_launch("gemm_bf16");
-    }
-    if (!ta && !tb) gemm_bf16<false, false><<<grid, T, 0, s>>>(A, B, C, M, N, lda, ldb, ldc, ks, ss, ep);
-    else if (ta && !tb) gemm_bf16<true, false><<<grid, T, 0, s>>>(A, B, C, M, N, lda, ldb, ldc, ks, ss, ep);
-    else if (!ta && tb) gemm_bf16<false, true><<<grid, T, 0, s>>>(A, B, C, M, N, lda, ldb, ldc, ks, ss, ep);
-    else gemm_bf16<true, true><<<grid, T, 0, s>>>(A, B, C, M, N, lda, ldb, ldc, ks, ss, ep);
+    if (!ta && !tb) gemm_bf16<false, false><<<grid, T, 0, s>>>(A, B, C, M, N, lda, ldb, ldc, ks, ss);
+    else if (ta && !tb) gemm_bf16<true, false><<<grid, T, 0, s>>>(A, B, C, M, N, lda, ldb, ldc, ks, ss);
+    else if (!ta && tb) gemm_bf16<false, true><<<grid, T, 0, s>>>(A, B, C, M, N, lda, ldb, ldc, ks, ss);
+    else gemm_bf16<true, true><<<grid, T, 0, s>>>(A, B, C, M, N, lda, ldb, ldc, ks, ss);
     return after_launch("gemm_bf16");
 }
 
@@ -198,116 +192,123 @@ int check_batch(const smrt_mlp* m, int32_t n)
     return SMRT_OK;
 }
 
-// Forward pass over n rows of points; the output goes to `out` ([n][outputs]).
-int forward(smrt_mlp* m, const float* pts, int n, float* out)
+// Output-column tile of the row-tile kernels: 128 where the width allows.
+int column_tile(int n) { return n % 128 == 0 ? 128 : 64; }
+
+// Forward pass over n rows of points.  Hidden activations go to m->a(l); the
+// output layer writes `out` ([n][outputs]) and, given a target, also the MSE
+// gradient m->dy() and the squared-error partials m->loss_part().
+int forward(smrt_mlp* m, const float* pts, int n, float* out, const float* target)
 {
+    using namespace smrt::mlp;
     const MlpLayout& L = m->L;
     hipStream_t s = m->stream;
-    smrt::mlp::features<<<blocks_for((int64_t)n * L.k0), 256, 0, s>>>(pts, m->fourier(), L.nf, n, L.k0, m->x0());
+    features<<<n / 64, 256, 0, s>>>(pts, m->fourier(), L.nf, n, L.k0, m->x0());
     int rc = after_launch("features");
     if (rc) return rc;
+    const int tiles = n / RT;
+    const int groups = std::min(tiles, kForwardGroups);
     for (int l = 0; l < L.layers; ++l) {
         const uint16_t* in = l == 0 ? m->x0() : m->a(l - 1);
         const int K = L.in[l], N = L.out[l];
-        // Z = in W + b with the bias and the activation in the product's epilogue
-        smrt::mlp::Epilogue ep;
-        ep.bias = m->params() + L.b_off[l];
-        const bool hidden = l < L.layers - 1;
-        if (hidden) {
-            ep.z = m->z(l);
-            ep.act = m->a(l);
+        const uint16_t* wt = m->wbf_t() + L.w_off[l];
+        const float* bias = m->params() + L.b_off[l];
+        FwdOut o;
+        if (l < L.layers - 1) {
+            o.act = m->a(l);
+            const int bn = column_tile(N);
+            dim3 grid(groups, N / bn);
+            if (bn == 128) layer_forward<128, FWD_HIDDEN><<<grid, ROW_THREADS, 0, s>>>(in, K, wt, bias, N, tiles, o);
+            else layer_forward<64, FWD_HIDDEN><<<grid, ROW_THREADS, 0, s>>>(in, K, wt, bias, N, tiles, o);
         } else {
-            ep.y = out;
-            ep.keep = L.outputs;
+            // the output layer is one 64-column tile (N == n_last == 64)
+            o.y = out;
+            o.keep = L.outputs;
+            dim3 grid(groups, 1);
+            if (target) {
+                o.target = target;
+                o.dy = m->dy();
+                o.scale = 2.0f / ((float)n * L.outputs);
+                o.loss = m->loss_part();
+                m->loss_parts = groups;
+                layer_forward<64, FWD_OUT_MSE><<<grid, ROW_THREADS, 0, s>>>(in, K, wt, bias, N, tiles, o);
+            } else {
+                layer_forward<64, FWD_OUT><<<grid, ROW_THREADS, 0, s>>>(in, K, wt, bias, N, tiles, o);
+            }
         }
-        rc = gemm(s, false, false, in, m->wbf() + L.w_off[l], nullptr, n, N, K, K, N, N, 1,
-                  hidden ? smrt::mlp::EPI_BIAS_SILU : smrt::mlp::EPI_BIAS_OUT, ep);
+        rc = after_launch("layer_forward");
         if (rc) return rc;
     }
     return SMRT_OK;
 }
 
-// Row splits of the weight-gradient products: as many as keep >= 128 rows
-// (four K-steps) per split, at most 512, so a 128 x 128 gradient of 65,536
-// rows runs 2048 workgroups.
-int splits_for(int n)
+// Row blocks of the weight-gradient products: as many as keep at least
+// kMinSplitRows rows (a multiple of 64) per block, at most L.max_splits.
+int splits_for(const MlpLayout& L, int n)
 {
-    int s = 512;
-    while (s > 1 && (n % (32 * s) || n / s < 128)) s >>= 1;
+    int s = L.max_splits;
+    while (s > 1 && (n % (smrt::mlp::WG_ROWS * s) || n / s < kMinSplitRows)) s >>= 1;
     return s;
 }
 
-// Column sums of a rows x cols array (row stride ld) into out[cols], in a
-// fixed order: passes of kReduceRows-row chunk sums (the first pass with
-// longer chunks when the chunk count would exceed the grid) until at most
-// kReduceRows rows remain, then one pass of plain sums.
-template <typename T>
-void reduce_columns(smrt_mlp* m, hipStream_t s, const T* in, int rows, int cols, int64_t ld, float* out)
+int launch_weight_grad(hipStream_t s, const uint16_t* X, const uint16_t* dZ, int M, int N, int n, int splits, float* part)
 {
-    constexpr int R = kReduceRows;
-    const int bx = (cols + 255) / 256;
-    if (rows <= R) {
-        smrt::mlp::column_sums<T><<<bx, 256, 0, s>>>(in, rows, cols, ld, out);
-        return;
-    }
-    const int r1 = std::max(R, (rows + 65534) / 65535); // keeps the grid's y dimension <= 65535
-    int chunks = (rows + r1 - 1) / r1;
-    smrt::mlp::column_sums_chunked<T><<<dim3(bx, chunks), 256, 0, s>>>(in, rows, cols, ld, r1, m->red(0));
-    const float* cur = m->red(0);
-    int which = 1;
-    rows = chunks;
-    while (rows > R) {
-        chunks = (rows + R - 1) / R;
-        smrt::mlp::column_sums_chunked<float><<<dim3(bx, chunks), 256, 0, s>>>(cur, rows, cols, cols, R,
-                                                                              m->red(which));
-        cur = m->red(which);
-        which ^= 1;
-        rows = chunks;
-    }
-    smrt::mlp::column_sums<float><<<bx, 256, 0, s>>>(cur, rows, cols, cols, out);
+    using namespace smrt::mlp;
+    const int bm = column_tile(M), bn = column_tile(N), rps = n / splits;
+    const int64_t stride = (int64_t)M * N + N;
+    dim3 grid(N / bn, M / bm, splits);
+    if (bm == 128 && bn == 128) weight_grad<128, 128><<<grid, ROW_THREADS, 0, s>>>(X, dZ, M, N, rps, part, stride);
+    else if (bm == 128) weight_grad<128, 64><<<grid, ROW_THREADS, 0, s>>>(X, dZ, M, N, rps, part, stride);
+    else if (bn == 128) weight_grad<64, 128><<<grid, ROW_THREADS, 0, s>>>(X, dZ, M, N, rps, part, stride);
+    else weight_grad<64, 64><<<grid, ROW_THREADS, 0, s>>>(X, dZ, M, N, rps, part, stride);
+    return after_launch("weight_grad");
 }
 
-// Backward pass after forward() wrote m->y(): fills m->grad() (padded layout)
-// and, when loss != NULL, the mean squared error (synchronizes).
-int backward(smrt_mlp* m, const float* target, int n, double* loss)
+// Backward pass after forward() with a target: the row-block partials of
+// every layer's W and b gradient in m->wpart(), then one pass that sums them
+// into m->grad() (adam null) or applies Adam; with loss != NULL also the mean
+// squared error (synchronizes).
+int backward(smrt_mlp* m, int n, const smrt::mlp::AdamArgs* adam, double* loss)
 {
+    using namespace smrt::mlp;
     const MlpLayout& L = m->L;
     hipStream_t s = m->stream;
-    smrt::mlp::mse_grad<<<L.loss_blocks, 256, 0, s>>>(m->y(), target, n, L.outputs, L.n_last, m->dy(),
-                                                      m->loss_part());
-    int rc = after_launch("mse_grad");
-    if (rc) return rc;
-    const int splits = splits_for(n);
+    const int splits = splits_for(L, n);
+    const int tiles = n / RT;
+    const int groups = std::min(tiles, kBackwardGroups);
     const uint16_t* dcur = m->dy();
     int flip = 0;
+    int rc = SMRT_OK;
     for (int l = L.layers - 1; l >= 0; --l) {
         const uint16_t* in = l == 0 ? m->x0() : m->a(l - 1);
         const int K = L.in[l], N = L.out[l];
-        // dW_l = in^T dZ_l and db_l = column sums of dZ_l, split over the rows
-        // (the bias partial beside each split's weight partial), then summed
-        // in split order into the layer's contiguous W, b gradient
-        const int64_t wb = (int64_t)K * N + N;
-        rc = gemm(s, true, false, in, dcur, m->wpart(), K, N, n, K, N, N, splits, smrt::mlp::EPI_STORE_DB, {}, wb);
-        if (rc) return rc;
-        reduce_columns<float>(m, s, m->wpart(), splits, (int)wb, wb, m->grad() + L.w_off[l]);
-        rc = after_launch("weight gradients");
+        rc = launch_weight_grad(s, in, dcur, K, N, n, splits, m->wpart() + (size_t)splits * L.w_off[l]);
         if (rc) return rc;
         if (l == 0) break;
-        // dZ_{l-1} = (dZ_l W_l^T) silu'(Z_{l-1}), the activation's derivative in
-        // the product's epilogue
+        // dZ_{l-1} = (dZ_l W_l^T) silu'(Z_{l-1}), Z_{l-1} = A_{l-2} W_{l-1} + b_{l-1}
+        const uint16_t* xp = l == 1 ? m->x0() : m->a(l - 2);
+        const int kp = L.in[l - 1];
         uint16_t* dnext = m->dz(flip);
         flip ^= 1;
-        smrt::mlp::Epilogue ep;
-        ep.z = m->z(l - 1);
-        ep.act = dnext;
-        rc = gemm(s, false, true, dcur, m->wbf() + L.w_off[l], nullptr, n, K, N, N, N, K, 1,
-                  smrt::mlp::EPI_SILU_GRAD, ep);
+        const int bn = column_tile(K);
+        dim3 grid(groups, K / bn);
+        const uint16_t* w = m->wbf() + L.w_off[l];
+        const uint16_t* wpt = m->wbf_t() + L.w_off[l - 1];
+        const float* bp = m->params() + L.b_off[l - 1];
+        if (bn == 128) layer_backward<128><<<grid, ROW_THREADS, 0, s>>>(dcur, N, w, xp, kp, wpt, bp, K, tiles, dnext);
+        else layer_backward<64><<<grid, ROW_THREADS, 0, s>>>(dcur, N, w, xp, kp, wpt, bp, K, tiles, dnext);
+        rc = after_launch("layer_backward");
         if (rc) return rc;
         dcur = dnext;
     }
+    const AdamArgs none;
+    reduce_adam<<<(int)((L.padded_params + 63) / 64), 256, 0, s>>>(m->wpart(), splits, L.table, m->grad(),
+                                                                   adam ? *adam : none);
+    rc = after_launch("reduce_adam");
+    if (rc) return rc;
     if (loss) {
-        m->loss_host.resize(L.loss_blocks);
-        HIP_TRY(hipMemcpyAsync(m->loss_host.data(), m->loss_part(), L.loss_blocks * sizeof(double),
+        m->loss_host.resize(m->loss_parts);
+        HIP_TRY(hipMemcpyAsync(m->loss_host.data(), m->loss_part(), m->loss_parts * sizeof(double),
                                hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         double acc = 0.0;
@@ -376,8 +377,9 @@ int smrt_mlp_create(const smrt_mlp_params* p, void* dev_ws, size_t ws_bytes, smr
         } else {
             hipError_t e = hipMalloc(reinterpret_cast<void**>(&m->ws), m->L.total);
             if (e != hipSuccess) {
-                delete m;
-                return fail(SMRT_ENOMEM, "hipMalloc(%zu): %s", m->L.total, hipGetErrorString(e));
+                const size_t total = m->L.total;
+                smrt_mlp_destroy(m);
+                return fail(SMRT_ENOMEM, "hipMalloc(%zu): %s", total, hipGetErrorString(e));
             }
             m->owns_ws = true;
         }
@@ -403,9 +405,9 @@ int smrt_mlp_set_params(smrt_mlp* m, const float* params, const float* fourier)
                                m->stream));
     int rc = convert_params(m, params, m->params(), 1);
     if (rc) return rc;
-    smrt::mlp::to_bf16<<<blocks_for((int64_t)L.padded_params), 256, 0, m->stream>>>(
-        m->params(), (int64_t)L.padded_params, m->wbf());
-    rc = after_launch("to_bf16");
+    smrt::mlp::weights_to_bf16<<<blocks_for((int64_t)L.padded_params), 256, 0, m->stream>>>(
+        m->params(), L.table, m->wbf(), m->wbf_t());
+    rc = after_launch("weights_to_bf16");
     if (rc) return rc;
     m->adam_steps = 0;
     m->has_params = true;
@@ -424,7 +426,7 @@ int smrt_mlp_forward(smrt_mlp* m, const float* points, int32_t n, float* out)
     if (!m || !points || !out) return fail(SMRT_EINVAL, "network, points or output is NULL");
     int rc = check_batch(m, n);
     if (rc) return rc;
-    return forward(m, points, n, out);
+    return forward(m, points, n, out, nullptr);
 }
 
 int smrt_mlp_gradient(smrt_mlp* m, const float* points, const float* target, int32_t n, float* grad,
@@ -433,8 +435,8 @@ int smrt_mlp_gradient(smrt_mlp* m, const float* points, const float* target, int
     if (!m || !points || !target || !grad) return fail(SMRT_EINVAL, "network, points, target or grad is NULL");
     int rc = check_batch(m, n);
     if (rc) return rc;
-    rc = forward(m, points, n, m->y());
-    if (!rc) rc = backward(m, target, n, loss);
+    rc = forward(m, points, n, m->y(), target);
+    if (!rc) rc = backward(m, n, nullptr, loss);
     if (!rc) rc = convert_params(m, m->grad(), grad, 0);
     return rc;
 }
@@ -445,15 +447,18 @@ int smrt_mlp_train_step(smrt_mlp* m, const float* points, const float* target, i
     if (!(lr > 0.0f) || !std::isfinite(lr)) return fail(SMRT_EINVAL, "learning rate must be positive");
     int rc = check_batch(m, n);
     if (rc) return rc;
-    rc = forward(m, points, n, m->y());
-    if (!rc) rc = backward(m, target, n, loss);
-    if (rc) return rc;
     m->adam_steps += 1;
     const double t = (double)m->adam_steps;
-    const float lr_t = (float)(lr * std::sqrt(1.0 - std::pow(0.999, t)) / (1.0 - std::pow(0.9, t)));
-    smrt::mlp::adam<<<blocks_for((int64_t)m->L.padded_params), 256, 0, m->stream>>>(
-        m->params(), m->grad(), m->adam_m(), m->adam_v(), (int64_t)m->L.padded_params, lr_t, m->wbf());
-    return after_launch("adam");
+    smrt::mlp::AdamArgs a;
+    a.w = m->params();
+    a.m = m->adam_m();
+    a.v = m->adam_v();
+    a.lr_t = (float)(lr * std::sqrt(1.0 - std::pow(0.999, t)) / (1.0 - std::pow(0.9, t)));
+    a.wbf = m->wbf();
+    a.wbf_t = m->wbf_t();
+    rc = forward(m, points, n, m->y(), target);
+    if (!rc) rc = backward(m, n, &a, loss);
+    return rc;
 }
 
 int smrt_gemm_bf16(const uint16_t* A, const uint16_t* B, float* C, int32_t M, int32_t N, int32_t K, int32_t lda,

@@ -36,10 +36,17 @@ def make_net(rng, fourier=16, width=128, layers=5, outputs=3):
     return dims, np.concatenate(params), rng.normal(0, 2.0, size=(fourier, 3))
 
 
-# Longest chain of binary32 additions in the library's sums over rows (weight
-# and bias gradients): at most 128 rows per split on the matrix cores, then
-# at most two fixed-order passes over at most 64 partial sums each.
-GRADIENT_DEPTH = 128 + 64 + 64
+def gradient_depth(n, max_splits=256):
+    """Longest chain of binary32 additions in the library's sums over n rows
+    (weight and bias gradients).  The library splits the rows into S blocks
+    (S = max_splits, halved until S divides n into blocks of at least 256
+    rows, a multiple of 64 each), accumulates each block on the matrix cores
+    (n / S additions), then sums the S partials in one pass in four
+    consecutive groups (S / 4 additions, then 3 to join the groups)."""
+    sp = max_splits
+    while sp > 1 and (n % (64 * sp) or n // sp < 256):
+        sp //= 2
+    return n // sp + sp // 4 + 4
 
 
 def test_forward_matches_oracle(smrt):
@@ -62,7 +69,7 @@ def test_forward_matches_oracle(smrt):
     assert np.all(used <= 1.0), np.argwhere(used > 1.0)[:10]
 
 
-@pytest.mark.parametrize("n", [1024, 65536])   # 8 and 512 row splits of the weight gradients
+@pytest.mark.parametrize("n", [1024, 8192, 65536])   # 4, 32 and 256 row blocks of the weight gradients
 def test_gradient_matches_oracle(smrt, n):
     """All 54,531 gradient entries and the loss within their tolerances of the
     bfloat16/binary32 model (oracle/mlp_oracle.py gradient_tolerance)."""
@@ -75,7 +82,7 @@ def test_gradient_matches_oracle(smrt, n):
         net.set_params(torch.tensor(params, device="cuda:0"), torch.tensor(B, device="cuda:0"))
         loss, g = net.gradient(torch.tensor(pts, device="cuda:0"), torch.tensor(tgt, device="cuda:0"))
         g = g.cpu().numpy().astype(np.float64)
-    want_loss, loss_tol, want, tol = M.gradient_tolerance(params, B, pts, tgt, dims, GRADIENT_DEPTH)
+    want_loss, loss_tol, want, tol = M.gradient_tolerance(params, B, pts, tgt, dims, gradient_depth(n))
     assert g.shape == want.shape == (54531,)
     used = np.abs(g - want) / tol
     scale = np.abs(want) + 1e-3 * np.abs(want).max()
@@ -83,6 +90,35 @@ def test_gradient_matches_oracle(smrt, n):
           "loss %.8f vs %.8f (tolerance %.1e)" % (used.max(), np.median(tol / scale), loss, want_loss, loss_tol))
     assert np.all(used <= 1.0), np.argwhere(used > 1.0)[:10]
     # the loss is summed in FP64 from binary32 errors in a block order
+    assert abs(loss - want_loss) <= loss_tol + 1e-12 * want_loss
+
+
+@pytest.mark.parametrize("fourier,width,layers,outputs,n", [
+    (4, 64, 3, 2, 512),      # 64-column tiles everywhere
+    (40, 256, 3, 3, 1024),   # 83 features padded to 128, two 128-column chunks, weights restaged per tile
+    (8, 192, 2, 1, 320),     # three 64-column tiles; one hidden layer; 320 rows: 5 row tiles, 1 block
+])
+def test_gradient_other_shapes(smrt, fourier, width, layers, outputs, n):
+    """Forward pass and every gradient entry within tolerance for networks
+    whose sizes take the other tile shapes and contraction chunkings."""
+    rng = np.random.default_rng(fourier + width + layers)
+    dims, params, B = make_net(rng, fourier=fourier, width=width, layers=layers, outputs=outputs)
+    params, B = params.astype(np.float32), B.astype(np.float32)
+    pts = rng.uniform(0, 1, size=(n, 3)).astype(np.float32)
+    tgt = rng.normal(0, 0.5, size=(n, outputs)).astype(np.float32)
+    with smrt.MLP(fourier=fourier, width=width, layers=layers, outputs=outputs, max_batch=n) as net:
+        net.set_params(torch.tensor(params, device="cuda:0"), torch.tensor(B, device="cuda:0"))
+        y = net.forward(torch.tensor(pts, device="cuda:0")).cpu().numpy().astype(np.float64)
+        loss, g = net.gradient(torch.tensor(pts, device="cuda:0"), torch.tensor(tgt, device="cuda:0"))
+        g = g.cpu().numpy().astype(np.float64)
+    want_y, tol_y = M.forward_tolerance(params, B, pts, dims)
+    assert np.all(np.abs(y - want_y) <= tol_y)
+    want_loss, loss_tol, want, tol = M.gradient_tolerance(params, B, pts, tgt, dims, gradient_depth(n))
+    assert g.shape == want.shape
+    used = np.abs(g - want) / tol
+    print("%s: largest fraction of the tolerance used %.3f (forward %.3f)"
+          % (dims, used.max(), (np.abs(y - want_y) / tol_y).max()))
+    assert np.all(used <= 1.0), np.argwhere(used > 1.0)[:10]
     assert abs(loss - want_loss) <= loss_tol + 1e-12 * want_loss
 
 
