@@ -76,13 +76,14 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget")
     ap.add_argument("--workload", default="tg",
-                    choices=["tg", "cavity", "precision", "batch", "warmstart", "small"],
+                    choices=["tg", "cavity", "precision", "batch", "warmstart", "small", "mlp"],
                     help="tg: periodic Taylor-Green throughput (default); cavity: lid-driven "
                          "cavity run from the cold start to the steady-state residual; "
                          "precision: one cavity in every storage type against FP64; "
                          "batch: many cavities of uneven size and Re run together to steady; "
                          "warmstart: learned warm start against the cold start; "
-                         "small: the 64^2 FP64 cavity at Re 100, eager and graph-captured")
+                         "small: the 64^2 FP64 cavity at Re 100, eager and graph-captured; "
+                         "mlp: one training step of the warm-start network on 65,536 rows")
     ap.add_argument("--train", type=int, default=200, help="warmstart: training cavities")
     ap.add_argument("--held-out", type=int, default=50, help="warmstart: evaluation cavities")
     ap.add_argument("--epochs", type=int, default=120, help="warmstart: training epochs")
@@ -94,7 +95,8 @@ def parse():
                     help="precision: step count at which the storage types are compared")
     ap.add_argument("--re", type=float, default=1000.0, help="cavity Reynolds number")
     ap.add_argument("--tol", type=float, default=1e-7, help="cavity steady-state residual")
-    ap.add_argument("--max-steps", type=int, default=3_000_000, help="cavity step cap")
+    ap.add_argument("--max-steps", type=int, default=None,
+                    help="cavity step cap (default 500,000 for the batch workload, 3,000,000 otherwise)")
     ap.add_argument("--no-extras", action="store_true",
                     help="default workload only: skip the six (scheme, tau) rates, the 1024^2 cavity's "
                          "time to steady and the warm-start study")
@@ -103,6 +105,8 @@ def parse():
     args = ap.parse_args()
     if args.storage is None:
         args.storage = "f32x" if args.workload == "cavity" else "f32"
+    if args.max_steps is None:
+        args.max_steps = 500_000 if args.workload == "batch" else 3_000_000
     return args
 
 
@@ -503,6 +507,36 @@ def batch_to_steady(args):
     print(json.dumps(out), flush=True)
 
 
+def mlp_step(args, rows=65536):
+    """Training steps of the warm-start network (5 layers of width 128,
+    16 Fourier features, bf16 matrix cores) on `rows` seeded synthetic points
+    and targets: `warmup` untimed steps, then `steps` timed with HIP events on
+    the network's stream."""
+    import torch
+    from paper_2409_01076_amd import warmstart as W
+    rng = np.random.default_rng(2409)
+    pts = torch.from_numpy(rng.uniform(0, 1, size=(rows, 3)).astype(np.float32)).to("cuda:0")
+    tgt = torch.from_numpy(rng.normal(0, 0.5, size=(rows, 3)).astype(np.float32)).to("cuda:0")
+    ws = W.WarmStart(fourier=16, width=128, layers=5, batch=rows)
+    for _ in range(max(1, args.warmup)):
+        ws.net.train_step(pts, tgt, 1e-3)
+    stream = ws.net.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        ws.net.train_step(pts, tgt, 1e-3)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    ws.close()
+    flops = 6.0 * rows * (64 * 128 + 3 * 128 * 128 + 128 * 64)  # forward + two backward products, padded sizes
+    return {"workload": "warm-start network training step: %d rows, 5 weight layers of width 128, "
+                        "16 Fourier features, bf16 matrix cores, Adam" % rows,
+            "steps": args.steps, "ms_per_step": round(ms, 4),
+            "tflops_padded": round(flops / (ms * 1e-3) / 1e12, 1)}
+
+
 def warm_start_study(args, quiet=False):
     """Learned warm start on 256^2 cavities: Re log-uniform in [100, 1e4]
     (seeded); args.train steady fields from the solver train the network on
@@ -610,6 +644,9 @@ def main():
         return
     if args.workload == "small":
         small_cavity(args)
+        return
+    if args.workload == "mlp":
+        print(json.dumps(mlp_step(args)), flush=True)
         return
 
     from paper_2409_01076_amd import inputs, smrt

@@ -329,12 +329,22 @@ int smrt_batch_run(smrt_batch* b, double tol, int64_t window, int64_t max_steps,
  * even number >= 2) of each candidate (the one-step shapes, and except for
  * FP64 storage the two-step kernel with 64 x 4, 64 x 8 and 64 x 16 tiles,
  * the three- and four-step kernels with 64 x 8 and 64 x 16 tiles and the
- * five-step kernel with 64 x 16 tiles); keeps the
- * fastest.
+ * five-step kernel with 64 x 16 and 64 x 22 tiles); keeps the fastest.
+ * Multi-step kernels take one tile a workgroup, so only the full grid is
+ * tried for them.
  * chosen (host [3], may be NULL) receives bx, by and the grid size;
  * smrt_batch_steps_per_launch reports the steps per launch.  The trial steps
  * advance every running cavity. */
 int smrt_batch_autotune(smrt_batch* b, int32_t steps, int32_t* chosen);
+
+/* Sets the batch's launch shape by hand: `steps` time steps per launch on
+ * tiles of bx x by nodes.  steps = 1: (bx, by) one of the one-step shapes
+ * (64 x 4, 128 x 2, 256 x 1, 32 x 8, 64 x 8, 128 x 4, 256 x 2, 512 x 1);
+ * steps = 2 .. 5 (not for FP64 storage): bx = 64 and by = 8, 16 or 22, or
+ * by = 4 with two steps.  Shorter remainder launches of a step count use the
+ * same tiles.  The grid becomes one workgroup per tile.  SMRT_EINVAL for
+ * other shapes; results are bitwise the same for every shape. */
+int smrt_batch_set_launch(smrt_batch* b, int32_t bx, int32_t by, int32_t steps);
 
 /* Fields of cavity `index` (dense device arrays [ny][nx], F32 or F64; any may
  * be NULL), from its current state. */

@@ -229,8 +229,8 @@ int upload_tables(smrt_batch* b)
 }
 
 // Threads per multi-step workgroup, as for single lattices: 768 for four-
-// and five-step tiles (64 x 8 and 64 x 16), 512 for other 64 x 16 tiles, 256
-// for smaller.
+// and five-step tiles (64 x 8, 64 x 16 and 64 x 22), 512 for other 64 x 16
+// and 64 x 22 tiles, 256 for smaller.
 constexpr int multi_threads(int steps, int ty) { return steps >= 4 && ty >= 8 ? 768 : ty >= 16 ? 512 : 256; }
 
 template <typename T, int SCHEME, int TY>
@@ -267,7 +267,7 @@ void launch_five_tile(smrt_batch* b, hipStream_t s, int parity, dim3 grid)
 
 template <typename T, int SCHEME> void launch_one(smrt_batch* b, hipStream_t s, int parity, dim3 grid)
 {
-    dim3 block(b->shape.bx, b->shape.by);
+    dim3 block(b->shape.bx, std::min(b->shape.by, 1024 / b->shape.bx)); // 64 x 22 tiles: two row passes
     smrt::batch_stream_collide<T, SCHEME><<<grid, block, 0, s>>>(b->desc(), b->table(), b->ntiles_dev(),
                                                                 reinterpret_cast<T*>(b->state()), parity, b->shape);
 }
@@ -276,22 +276,26 @@ template <typename T, int SCHEME>
 void launch_multi_or_one(smrt_batch* b, hipStream_t s, int parity, int k, dim3 grid)
 {
     if (k == 5) {
-        if (b->shape.by == 16) launch_five_tile<T, SCHEME, 16>(b, s, parity, grid);
+        if (b->shape.by == 22) launch_five_tile<T, SCHEME, 22>(b, s, parity, grid);
+        else if (b->shape.by == 16) launch_five_tile<T, SCHEME, 16>(b, s, parity, grid);
         else launch_five_tile<T, SCHEME, 8>(b, s, parity, grid);
         return;
     }
     if (k == 4) {
-        if (b->shape.by == 16) launch_four_tile<T, SCHEME, 16>(b, s, parity, grid);
+        if (b->shape.by == 22) launch_four_tile<T, SCHEME, 22>(b, s, parity, grid);
+        else if (b->shape.by == 16) launch_four_tile<T, SCHEME, 16>(b, s, parity, grid);
         else launch_four_tile<T, SCHEME, 8>(b, s, parity, grid);
         return;
     }
     if (k == 3) {
-        if (b->shape.by == 16) launch_three_tile<T, SCHEME, 16>(b, s, parity, grid);
+        if (b->shape.by == 22) launch_three_tile<T, SCHEME, 22>(b, s, parity, grid);
+        else if (b->shape.by == 16) launch_three_tile<T, SCHEME, 16>(b, s, parity, grid);
         else launch_three_tile<T, SCHEME, 8>(b, s, parity, grid);
         return;
     }
     if (k == 2) {
-        if (b->shape.by == 16) launch_two_tile<T, SCHEME, 16>(b, s, parity, grid);
+        if (b->shape.by == 22) launch_two_tile<T, SCHEME, 22>(b, s, parity, grid);
+        else if (b->shape.by == 16) launch_two_tile<T, SCHEME, 16>(b, s, parity, grid);
         else if (b->shape.by == 8) launch_two_tile<T, SCHEME, 8>(b, s, parity, grid);
         else launch_two_tile<T, SCHEME, 4>(b, s, parity, grid);
         return;
@@ -299,13 +303,17 @@ void launch_multi_or_one(smrt_batch* b, hipStream_t s, int parity, int k, dim3 g
     launch_one<T, SCHEME>(b, s, parity, grid);
 }
 
-// One launch of k time steps (k = 2 .. 5: 64 x shape.by tiles; the tile
+// One launch of k time steps (k = 2 .. 5: 64 x shape.by tiles, one a
+// workgroup; the tile
 // table is built for that shape, so a shorter remainder launch uses the same
 // table).  FP64 batches take one step per launch (multi_steps), so their
 // multi-step kernels are not built.
 template <typename T, int SCHEME> void launch_typed_scheme(smrt_batch* b, hipStream_t s, int parity, int k)
 {
-    dim3 grid((unsigned)std::max(b->grid, 1));
+    // the multi-step kernels take one tile a workgroup: never fewer
+    // workgroups than tiles, and a multiple of 8 (their XCD-contiguous order)
+    const int g = k > 1 ? (std::max(b->grid, b->ntiles) + 7) / 8 * 8 : b->grid;
+    dim3 grid((unsigned)std::max(g, 1));
     if constexpr (!std::is_same_v<T, double>) launch_multi_or_one<T, SCHEME>(b, s, parity, k, grid);
     else launch_one<T, SCHEME>(b, s, parity, grid);
 }
@@ -385,7 +393,7 @@ int enqueue_steps(smrt_batch* b, int64_t n)
 template <typename T> void launch_reduce_typed(smrt_batch* b, int update)
 {
     const int grid = std::min(b->ntiles, 4096);
-    dim3 block(b->shape.bx, b->shape.by);
+    dim3 block(b->shape.bx, std::min(b->shape.by, 1024 / b->shape.bx)); // 64 x 22 tiles: two row passes
     smrt::batch_reduce_partials<T><<<grid, block, 0, b->stream>>>(b->desc(), b->table(), b->ntiles_dev(),
                                                                   reinterpret_cast<const T*>(b->state()), b->parity,
                                                                   b->shape, b->snap(), update, b->partials());
@@ -507,10 +515,12 @@ int smrt_batch_create(const smrt_batch_params* p, void* dev_ws, size_t ws_bytes,
             return hip_fail(e, "hipMemsetAsync");
         }
         // Default launch: one pass over the table per launch; FP64 one step
-        // per launch with 64 x 4 tiles, other storage 64 x 16 tiles with five
-        // steps per launch (FP32) or three (16-bit); the autotuner chose five
-        // steps with 64 x 16 tiles for FP32 batches of 16 to 256 cavities.
-        b->shape = p->storage == SMRT_F64 ? kShapes[0] : smrt::BatchLaunch{64, 16};
+        // per launch with 64 x 4 tiles, FP32 64 x 22 tiles with five steps
+        // per launch (the autotuner's choice for 256 cavities of 64 .. 512
+        // nodes a side), 16-bit storage 64 x 16 tiles with three.
+        b->shape = p->storage == SMRT_F64 ? kShapes[0]
+                   : p->storage == SMRT_F32 ? smrt::BatchLaunch{64, 22}
+                                            : smrt::BatchLaunch{64, 16};
         b->multi = p->storage == SMRT_F64 ? 1 : p->storage == SMRT_F32 ? 5 : 3;
         int64_t total_tiles = 0;
         for (const auto& c : b->plan.desc) total_tiles += tiles_of(c.nx, c.ny, b->shape);
@@ -620,13 +630,14 @@ int smrt_batch_autotune(smrt_batch* b, int32_t steps, int32_t* chosen)
     int best_grid = b->grid;
     int best_multi = b->multi;
     int rc = SMRT_OK;
-    // Candidates: every one-step shape, then (except for FP64) the two-step
-    // kernel with 64 x 4, 64 x 8 and 64 x 16 tiles, the three- and four-step
-    // kernels with 64 x 8 and 64 x 16 tiles and the five-step kernel with
-    // 64 x 16 tiles; times are per time step.
-    static const int kMultiSteps[] = {2, 2, 2, 3, 3, 4, 4, 5};
-    static const int kMultiRows[] = {4, 8, 16, 8, 16, 8, 16, 16};
-    const int n_multi = b->p.storage == SMRT_F64 ? 0 : 8;
+    // Candidates: every one-step shape (with four grid sizes), then (except
+    // for FP64) the two-step kernel with 64 x 4, 64 x 8 and 64 x 16 tiles,
+    // the three- and four-step kernels with 64 x 8 and 64 x 16 tiles and the
+    // five-step kernel with 64 x 16 and 64 x 22 tiles (one tile a workgroup,
+    // so the full grid only); times are per time step.
+    static const int kMultiSteps[] = {2, 2, 2, 3, 3, 4, 4, 5, 5};
+    static const int kMultiRows[] = {4, 8, 16, 8, 16, 8, 16, 16, 22};
+    const int n_multi = b->p.storage == SMRT_F64 ? 0 : 9;
     for (int s = 0; s < kNumShapes + n_multi && rc == SMRT_OK; ++s) {
         const int multi = s >= kNumShapes ? kMultiSteps[s - kNumShapes] : 1;
         b->shape = multi > 1 ? smrt::BatchLaunch{64, kMultiRows[s - kNumShapes]} : kShapes[s];
@@ -638,7 +649,7 @@ int smrt_batch_autotune(smrt_batch* b, int32_t steps, int32_t* chosen)
                              cus * std::max(1, 32 / per_block_waves)};
         for (int gi = 0; gi < 4; ++gi) {
             b->grid = std::min(grids[gi], b->ntiles);
-            if (gi > 0 && grids[gi] >= b->ntiles) continue; // same as the full grid
+            if (gi > 0 && (multi > 1 || grids[gi] >= b->ntiles)) continue; // full grid only / same as it
             const int unit = multi;
             const int launches = std::max(2, steps / unit) & ~1; // even: parity kept
             launch_step(b, b->stream, b->parity, unit); // warm-up pair
@@ -673,6 +684,26 @@ int smrt_batch_autotune(smrt_batch* b, int32_t steps, int32_t* chosen)
         chosen[1] = b->shape.by;
         chosen[2] = b->grid;
     }
+    return SMRT_OK;
+}
+
+int smrt_batch_set_launch(smrt_batch* b, int32_t bx, int32_t by, int32_t steps)
+{
+    if (!b) return fail(SMRT_EINVAL, "batch is NULL");
+    bool ok = false;
+    if (steps == 1) {
+        for (const auto& sh : kShapes) ok |= sh.bx == bx && sh.by == by;
+    } else if (steps >= 2 && steps <= 5 && b->p.storage != SMRT_F64 && bx == 64) {
+        ok = by == 8 || by == 16 || by == 22 || (by == 4 && steps == 2);
+    }
+    if (!ok)
+        return fail(SMRT_EINVAL, "batch launch %d x %d with %d steps is not built for this storage", bx, by, steps);
+    b->shape = smrt::BatchLaunch{bx, by};
+    b->multi = steps;
+    const int rc = upload_tables(b);
+    if (rc) return rc;
+    b->grid = std::max(b->ntiles, 1);
+    drop_graphs(b);
     return SMRT_OK;
 }
 

@@ -29,7 +29,7 @@ EXPORTED = (
     "smrt_last_error", "smrt_copy_kernel",
     "smrt_batch_workspace_bytes", "smrt_batch_create", "smrt_batch_step", "smrt_batch_run",
     "smrt_batch_autotune", "smrt_batch_moments", "smrt_batch_init_fields", "smrt_batch_steps_done",
-    "smrt_batch_running", "smrt_batch_steps_per_launch", "smrt_batch_destroy",
+    "smrt_batch_running", "smrt_batch_steps_per_launch", "smrt_batch_set_launch", "smrt_batch_destroy",
     "smrt_mlp_param_count", "smrt_mlp_workspace_bytes", "smrt_mlp_create", "smrt_mlp_set_params",
     "smrt_mlp_get_params", "smrt_mlp_forward", "smrt_mlp_gradient", "smrt_mlp_train_step",
     "smrt_mlp_destroy", "smrt_gemm_bf16",
@@ -128,6 +128,7 @@ def load():
         "smrt_batch_steps_done": (i64, [vp]),
         "smrt_batch_running": (i32, [vp]),
         "smrt_batch_steps_per_launch": (i32, [vp]),
+        "smrt_batch_set_launch": (ctypes.c_int, [vp, i32, i32, i32]),
         "smrt_batch_destroy": (None, [vp]),
         "smrt_mlp_param_count": (ctypes.c_size_t, [ctypes.POINTER(MlpParams)]),
         "smrt_mlp_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(MlpParams)]),
@@ -491,6 +492,10 @@ class Batch:
         chosen = (ctypes.c_int32 * 3)()
         _check(load().smrt_batch_autotune(self._ctx, int(steps), chosen))
         return tuple(chosen)
+
+    def set_launch(self, bx, by, steps):
+        """Launch shape by hand: `steps` time steps per launch on bx x by tiles."""
+        _check(load().smrt_batch_set_launch(self._ctx, int(bx), int(by), int(steps)))
 
     def moments(self, index, dtype=torch.float64):
         s = (self.ny[index], self.nx[index])

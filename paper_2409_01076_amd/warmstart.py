@@ -14,8 +14,8 @@ rescaled so the total mass equals the cold start's (N^2): the closed cavity
 conserves mass, so the initial mass fixes the final state.
 
 Only orchestration lives here: every arithmetic step of training and
-inference runs in the library's kernels; numpy handles index shuffling and
-host-side bookkeeping.
+inference runs in the library's kernels; numpy draws the shuffle order (a
+device gather applies it) and does the host-side bookkeeping.
 """
 import math
 import time
@@ -77,9 +77,10 @@ class WarmStart:
         if bs == 0:
             raise ValueError("need at least 64 training rows")
         n = (points.shape[0] // bs) * bs
-        order = np.random.default_rng(seed).permutation(points.shape[0])[:n]
-        P = torch.from_numpy(np.ascontiguousarray(points[order])).to(self.device)
-        T = torch.from_numpy(np.ascontiguousarray(target[order])).to(self.device)
+        order = torch.from_numpy(np.random.default_rng(seed).permutation(points.shape[0])[:n]).to(self.device)
+        # shuffled on the device: one upload of the rows, then a gather
+        P = torch.from_numpy(np.ascontiguousarray(points, dtype=np.float32)).to(self.device)[order].contiguous()
+        T = torch.from_numpy(np.ascontiguousarray(target, dtype=np.float32)).to(self.device)[order].contiguous()
         per_epoch = n // bs
         total = epochs * per_epoch
         history = []

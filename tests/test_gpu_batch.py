@@ -47,7 +47,7 @@ def test_autotune_keeps_results_bitwise(smrt):
     nx, ny = zip(*SIZES)
     with smrt.Batch(nx, ny, scheme="smrt", storage="f32", re=RES, u_lid=0.1) as b:
         bx, by, grid = b.autotune(steps=6)
-        assert bx * by in (256, 512, 1024) and grid >= 1 and b.steps_per_launch in (1, 2, 3, 4, 5)
+        assert bx * by in (256, 512, 1024, 1408) and grid >= 1 and b.steps_per_launch in (1, 2, 3, 4, 5)
         done = b.steps_done
         b.step(130 - done if done < 130 else 0)
         steps = b.steps_done
@@ -56,6 +56,37 @@ def test_autotune_keeps_results_bitwise(smrt):
         want = single_run(smrt, x, y, re, steps)
         for g, w in zip(got[i], want):
             assert np.array_equal(g, w), i
+
+
+@pytest.mark.parametrize("bx,by,steps", [(64, 22, 5), (64, 22, 4), (64, 22, 3), (64, 22, 2), (64, 16, 5),
+                                          (64, 8, 4), (64, 4, 2), (128, 2, 1)])
+def test_set_launch_keeps_results_bitwise(smrt, bx, by, steps):
+    """Every tile shape, with graph replays and shorter remainder launches
+    (one-step remainders on 64 x 22 tables take two row passes a block)."""
+    nx, ny = zip(*SIZES)
+    with smrt.Batch(nx, ny, scheme="smrt", storage="f32", re=RES, u_lid=0.1) as b:
+        b.set_launch(bx, by, steps)
+        assert b.steps_per_launch == steps
+        n = 64 * steps + steps + 1 if steps > 1 else 70   # one graph, one full launch, remainders
+        for chunk in (n, 1, steps - 1 if steps > 1 else 1):
+            b.step(chunk)
+        total = b.steps_done
+        got = [[t.cpu().numpy() for t in b.moments(i)] for i in range(len(SIZES))]
+    for i, ((x, y), re) in enumerate(zip(SIZES, RES)):
+        want = single_run(smrt, x, y, re, total)
+        for g, w in zip(got[i], want):
+            assert np.array_equal(g, w), (i, bx, by, steps)
+
+
+def test_set_launch_rejects_unbuilt_shapes(smrt):
+    with smrt.Batch([64], [64], scheme="smrt", storage="f32", re=[100.0], u_lid=0.1) as b:
+        for bx, by, steps in [(64, 22, 1), (64, 12, 5), (32, 22, 5), (64, 4, 3), (64, 16, 6)]:
+            with pytest.raises(smrt.SmrtError):
+                b.set_launch(bx, by, steps)
+    with smrt.Batch([64], [64], scheme="smrt", storage="f64", re=[100.0], u_lid=0.1) as b:
+        with pytest.raises(smrt.SmrtError):
+            b.set_launch(64, 16, 5)
+        b.set_launch(64, 8, 1)
 
 
 def test_batch_cavity_against_oracle(smrt):

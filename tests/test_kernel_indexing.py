@@ -212,8 +212,10 @@ def test_multi_step_kernels_fp64(S, TX, TY):
 
 
 # batch launch shapes (smrt_batch.hip): one-step blocks, multi-step tiles (no FP64)
-BATCH_BLOCKS = [(64, 4), (128, 2), (256, 1), (32, 8), (64, 8), (128, 4), (256, 2), (512, 1)]
-BATCH_TILES = [(2, 64, 4), (2, 64, 8), (2, 64, 16), (3, 64, 8), (3, 64, 16), (4, 64, 8), (4, 64, 16), (5, 64, 16)]
+BATCH_BLOCKS = [(64, 4), (128, 2), (256, 1), (32, 8), (64, 8), (128, 4), (256, 2), (512, 1),
+                (64, 16), (64, 22)]   # one-step remainders on multi-step tables (64 x 22: two row passes)
+BATCH_TILES = [(2, 64, 4), (2, 64, 8), (2, 64, 16), (3, 64, 8), (3, 64, 16), (4, 64, 8), (4, 64, 16), (5, 64, 16),
+               (2, 64, 22), (3, 64, 22), (4, 64, 22), (5, 64, 22)]
 BATCH_SIZES = [3, 17, 64, 65, 100, 157, 300]
 
 
@@ -271,6 +273,28 @@ def test_tile_order_visits_every_tile_once(tiles_x, tiles_y, P):
 # --- moment storage (stream_collide_mom, paper_2409_01076_amd/csrc/moment_kernels.hpp) -----
 
 MOM_TX = 64
+
+
+@pytest.mark.parametrize("grid", [8, 16, 24, 12456, 16960])
+def test_batch_xcd_order_visits_every_tile_once(grid):
+    """batch_multi's workgroup-to-tile map: with n tiles listed and
+    c = ceil(n / 8), workgroup b takes tile (b mod 8) c + b / 8 (none when
+    b / 8 >= c), for a grid that is a multiple of 8 and at least n: every
+    listed tile exactly once, each XCD (b mod 8) one contiguous run, and the
+    runs spread over all 8 XCDs however far the table has shrunk."""
+    assert grid % 8 == 0
+    b = np.arange(grid)
+    for ntiles in sorted(n for n in {1, 5, 9, grid // 3, grid - 7, grid} if 1 <= n <= grid):
+        c = (ntiles + 7) // 8
+        t = np.where(b // 8 < c, (b % 8) * c + b // 8, ntiles)
+        got = t[t < ntiles]
+        assert np.array_equal(np.sort(got), np.arange(ntiles))
+        per_xcd = [t[(b % 8 == x) & (t < ntiles)] for x in range(8)]
+        for run in per_xcd:
+            assert np.all(np.diff(run) == 1)
+        assert max(len(r) for r in per_xcd) <= c
+        busy = sum(len(r) > 0 for r in per_xcd)
+        assert busy == min(8, -(-ntiles // c))
 
 
 @pytest.mark.parametrize("mom_ty", [8, 16])
