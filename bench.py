@@ -44,6 +44,14 @@ VALU_FILE = os.path.join(ROOT, "profiles", "valu_stream_collide.json")
 # 2.4 GHz.  Packed FP32 instructions are disabled in this build, so every
 # FP32 operation is one such instruction.
 VALU_PEAK_G = 256 * 4 * 2.4 / 4
+# Lane operations of one SmrtLBM node-update in FP32 (collide<SMRT>), an FMA
+# or a reciprocal counting as one: 8 pair sums and differences, 4 for the
+# density, 4 for the momentum, 2 for 1/rho, 2 for u, 3 products j u, 2 for
+# j.u and the equilibrium base, 3 + 4 for the axis and diagonal equilibrium
+# parts, 4 + 4 for the odd parts, 5 for the two group sums, 2 for the
+# corrections, 4 + 8 to assemble the eight moving populations and 8 for the
+# rest population from the density.
+SMRT_VALU_OPS = 67
 STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2, "f32x": 4}
 # moment storage: bytes a node reads and writes per step (3 moments + 2 amplitudes)
 MOMENT_NODE_BYTES = {"m64": 40, "m16": 16, "mbf16": 16}
@@ -767,13 +775,14 @@ def main():
     }
     out["roofline"]["frac_of_copy_kernel"] = round(achieved / out["copy_kernel_gbs"], 4)
     if valu is not None:
-        # The vector-instruction ceiling.  Algorithmic instructions: a node
-        # advanced spl steps costs spl times the one-step kernel's VALU
-        # instructions per node-update (its collision, streaming and
-        # addressing, no ring recomputation); issued: what the counters
-        # recorded for the multi-step launch (rings and LDS addressing too).
-        per_update = valu["one_step_wave_insts_per_launch"] / cells
-        alg_insts = per_update * spl * cells
+        # The vector-instruction ceiling.  Algorithmic: the SmrtLBM collision's
+        # own arithmetic, SMRT_VALU_OPS lane operations a node-update (moments,
+        # equilibrium terms, the two group corrections, the rest population;
+        # streaming is data movement), as wave-instruction equivalents (64 lanes
+        # each).  Issued: what SQ_INSTS_VALU recorded for this launch (ring
+        # recomputation, LDS addressing and conversions too).  The ceiling that
+        # the issued instructions come closer to binds.
+        alg_insts = SMRT_VALU_OPS / 64.0 * spl * cells
         alg_g = alg_insts / (launch_ms / 1e3) / 1e9
         issued_g = valu["multi_wave_insts_per_launch"] / (launch_ms / 1e3) / 1e9
         hbm = {k: out["roofline"][k] for k in ("achieved", "peak", "unit", "frac")}
@@ -782,8 +791,8 @@ def main():
             "achieved": round(alg_g, 1), "peak": VALU_PEAK_G, "unit": "G wave-instructions/s",
             "frac": round(alg_g / VALU_PEAK_G, 4),
             "algorithmic_wave_insts_per_launch": round(alg_insts),
-            "algorithmic_unit": "one node advanced %d time steps: %d x the one-step kernel's %.2f lane "
-                                "instructions per node-update" % (spl, spl, per_update * 64),
+            "algorithmic_unit": "one node advanced %d time steps: %d x %d lane operations of the SmrtLBM "
+                                "collision per node-update, / 64 lanes" % (spl, spl, SMRT_VALU_OPS),
             "issued_wave_insts_per_launch": valu["multi_wave_insts_per_launch"],
             "issued_g": round(issued_g, 1), "issued_frac": round(issued_g / VALU_PEAK_G, 4),
             "source": "SQ_INSTS_VALU, profiles/valu_stream_collide.json",
