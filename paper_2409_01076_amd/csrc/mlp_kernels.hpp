@@ -12,12 +12,14 @@
 //   layer_forward   A_l = silu(A_{l-1} W_l + b_l) (bf16); for the output
 //                   layer Y = A W + b, with the MSE gradient dY and the
 //                   squared-error partials in the same epilogue
-//   layer_backward  dZ_{l-1} = (dZ_l W_l^T) silu'(Z_{l-1}), where
+//   backward_and_grad  dZ_{l-1} = (dZ_l W_l^T) silu'(Z_{l-1}), where
 //                   Z_{l-1} = A_{l-2} W_{l-1} + b_{l-1} is recomputed with the
 //                   forward pass's own instruction sequence (bitwise the
 //                   forward value, so Z is never stored)
-//   weight_grad     per block of rows: A_{l-1}^T dZ_l and the column sums of
-//                   dZ_l (the weight and bias gradient partials)
+//                   and in the same grid, per block of rows, A_{l-1}^T dZ_l
+//                   and the column sums of dZ_l (the weight and bias
+//                   gradient partials)
+//   weight_grad     the same partials for the first layer
 //   reduce_adam     the row-block partials of every layer summed in a fixed
 //                   order, then Adam
 // The row-tile kernels keep a layer's weights resident in LDS and read every
@@ -382,20 +384,34 @@ __global__ void __launch_bounds__(ROW_THREADS, 3) layer_forward(const uint16_t* 
 // with dZ [rows][N], W = W_l ([K][N] bf16), Xp = A_{l-2} or X0 ([rows][Kp]),
 // Wpt = W_{l-1}^T ([K][Kp] bf16).  z is accumulated exactly as layer_forward
 // accumulated it (same chunks, same operand order).  Grid: (row groups, K / BN).
+struct BackArgs {
+    const uint16_t* dZ;
+    int N;
+    const uint16_t* W;
+    const uint16_t* Xp;
+    int Kp;
+    const uint16_t* Wpt;
+    const float* bp;
+    int K, tiles;
+    uint16_t* dZout;
+};
+
+// The input-gradient tiles of workgroup (bx, by) of a (gx, K / BN) grid,
+// with its LDS: Wz and Wg BN x WS elements each, bs BN floats.
 template <int BN>
-__global__ void __launch_bounds__(ROW_THREADS) layer_backward(const uint16_t* __restrict__ dZ, int N,
-                                                              const uint16_t* __restrict__ W,
-                                                              const uint16_t* __restrict__ Xp, int Kp,
-                                                              const uint16_t* __restrict__ Wpt,
-                                                              const float* __restrict__ bp, int K, int tiles,
-                                                              uint16_t* __restrict__ dZout)
+__device__ __forceinline__ void backward_tiles(const BackArgs& a, int bx, int by, int gx, uint16_t* Wz, uint16_t* Wg,
+                                               float* bs)
 {
+    const uint16_t* __restrict__ dZ = a.dZ;
+    const uint16_t* __restrict__ W = a.W;
+    const uint16_t* __restrict__ Xp = a.Xp;
+    const uint16_t* __restrict__ Wpt = a.Wpt;
+    const float* __restrict__ bp = a.bp;
+    uint16_t* __restrict__ dZout = a.dZout;
+    const int N = a.N, Kp = a.Kp, K = a.K, tiles = a.tiles;
     constexpr int FJ = BN / 16;
-    __shared__ __attribute__((aligned(16))) uint16_t Wz[BN * WS];
-    __shared__ __attribute__((aligned(16))) uint16_t Wg[BN * WS];
-    __shared__ __attribute__((aligned(16))) float bs[BN];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
-    const int n0 = blockIdx.y * BN;
+    const int n0 = by * BN;
     const int cz = (Kp + KC - 1) / KC, cg = (N + KC - 1) / KC;
     if (threadIdx.x < BN) bs[threadIdx.x] = bp[n0 + threadIdx.x];
     const auto epilogue = [&](const f32x4 (&z)[FJ], const f32x4 (&g)[FJ], int tile) {
@@ -420,14 +436,14 @@ __global__ void __launch_bounds__(ROW_THREADS) layer_backward(const uint16_t* __
         bf16x8 nz[KC / 32], ng[KC / 32];
         stage_chunk(Wz, Wpt, Kp, n0, BN, 0, Kp);
         stage_chunk(Wg, W, N, n0, BN, 0, N);
-        int tile = blockIdx.x;
+        int tile = bx;
         if (tile < tiles) {
             load_rows(xz, Xp, Kp, tile * RT + wave * 16, 0, Kp);
             load_rows(xg, dZ, N, tile * RT + wave * 16, 0, N);
         }
         __syncthreads();
-        for (; tile < tiles; tile += gridDim.x) {
-            const int next = tile + gridDim.x;
+        for (; tile < tiles; tile += gx) {
+            const int next = tile + gx;
             if (next < tiles) {
                 load_rows(nz, Xp, Kp, next * RT + wave * 16, 0, Kp);
                 load_rows(ng, dZ, N, next * RT + wave * 16, 0, N);
@@ -445,7 +461,7 @@ __global__ void __launch_bounds__(ROW_THREADS) layer_backward(const uint16_t* __
             }
         }
     } else {
-        for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        for (int tile = bx; tile < tiles; tile += gx) {
             const int m0 = tile * RT + wave * 16;
             f32x4 z[FJ], g[FJ];
 #pragma unroll
@@ -471,6 +487,7 @@ __global__ void __launch_bounds__(ROW_THREADS) layer_backward(const uint16_t* __
     }
 }
 
+
 // Row-block partials of a layer's gradient: for split s (rows
 // [s rps, (s + 1) rps), rps a multiple of 64), output tile (m, n) of
 //   part[s][m][n] = sum over the block's rows r of X[r][m] dZ[r][n]
@@ -487,24 +504,43 @@ __global__ void __launch_bounds__(ROW_THREADS) layer_backward(const uint16_t* __
 // 16-byte loads a thread) are in flight during the current slice's
 // products, with one barrier a slice.
 constexpr int WG_ROWS = 64;
+struct GradArgs {
+    const uint16_t* X;
+    const uint16_t* dZ;
+    int M, N, rps;
+    float* part;
+    int64_t split_stride;
+};
+
+template <int BM, int BN> struct GradLds {
+    static constexpr int RS = WG_ROWS / 2 + 4; // words per staged column
+    uint32_t Xt[2][BM * RS];
+    uint32_t Dt[2][BN * RS];
+    float dbh[2][BN];
+};
+
+// The weight-gradient partials of block (bx, by, bz) of a (N / BN, M / BM, splits) grid.
 template <int BM, int BN>
-__global__ void __launch_bounds__(ROW_THREADS) weight_grad(const uint16_t* __restrict__ X,
-                                                           const uint16_t* __restrict__ dZ, int M, int N, int rps,
-                                                           float* __restrict__ part, int64_t split_stride)
+__device__ __forceinline__ void grad_partials(const GradArgs& a, int bx, int by, int bz, GradLds<BM, BN>& L)
 {
-    constexpr int RS = WG_ROWS / 2 + 4; // words per staged column
+    const uint16_t* __restrict__ X = a.X;
+    const uint16_t* __restrict__ dZ = a.dZ;
+    float* __restrict__ part = a.part;
+    const int M = a.M, N = a.N, rps = a.rps;
+    const int64_t split_stride = a.split_stride;
+    constexpr int RS = GradLds<BM, BN>::RS;
     constexpr int FI = BM / 32, FJ = BN / 32;
-    __shared__ __attribute__((aligned(16))) uint32_t Xt[2][BM * RS];
-    __shared__ __attribute__((aligned(16))) uint32_t Dt[2][BN * RS];
-    __shared__ float dbh[2][BN];
+    auto& Xt = L.Xt;
+    auto& Dt = L.Dt;
+    auto& dbh = L.dbh;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r = lane & 15, q = lane >> 4;
-    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-    const int64_t r0 = (int64_t)blockIdx.z * rps;
+    const int m0 = by * BM, n0 = bx * BN;
+    const int64_t r0 = (int64_t)bz * rps;
     const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
     // loader: row pairs j and j + 16, columns c8 .. c8 + 7 of the tile
     const int j = tid & 15, c8 = (tid >> 4) * 8;
     const bool lx = c8 < BM, ldz = c8 < BN;
-    const bool db_blk = blockIdx.y == 0;
+    const bool db_blk = by == 0;
     const int dn = tid % BN, dh = tid / BN; // bias-gradient column and half of the slice's rows
     u32x4 xa[2], xb[2], da[2], db[2];
     const auto load = [&](int s) {
@@ -570,7 +606,7 @@ __global__ void __launch_bounds__(ROW_THREADS) weight_grad(const uint16_t* __res
                 for (int fj = 0; fj < FJ; ++fj) acc[fi][fj] = mfma(df[fj], xf[fi], acc[fi][fj]);
         }
     }
-    float* Cs = part + (int64_t)blockIdx.z * split_stride;
+    float* Cs = part + (int64_t)bz * split_stride;
 #pragma unroll
     for (int fi = 0; fi < FI; ++fi)
 #pragma unroll
@@ -583,6 +619,46 @@ __global__ void __launch_bounds__(ROW_THREADS) weight_grad(const uint16_t* __res
         if (tid < 2 * BN) dbh[dh][dn] = dsum;
         __syncthreads();
         if (tid < BN) Cs[(int64_t)M * N + n0 + tid] = dbh[0][tid] + dbh[1][tid];
+    }
+}
+
+
+template <int BM, int BN>
+__global__ void __launch_bounds__(ROW_THREADS) weight_grad(GradArgs a)
+{
+    __shared__ __attribute__((aligned(16))) GradLds<BM, BN> L;
+    grad_partials<BM, BN>(a, blockIdx.x, blockIdx.y, blockIdx.z, L);
+}
+
+// An input-gradient layer and the weight-gradient partials of the same
+// layer in one grid: both read dZ_l and neither waits on the other, and both
+// are bound by memory latency, so sharing CUs overlaps their waits.  The
+// two kinds of workgroup are spread evenly over the grid; the LDS is one
+// buffer that each role lays out for itself.  nb = gx_back x gy_back input-gradient workgroups (gx_back
+// row groups), ng = gx x gy x gz gradient workgroups.
+template <int BN, int BM2, int BN2>
+__global__ void __launch_bounds__(ROW_THREADS, 2) backward_and_grad(BackArgs ba, int gx_back, int gy_back, GradArgs ga,
+                                                                 int gx, int gy, int gz)
+{
+    constexpr size_t kBack = 2 * BN * WS * sizeof(uint16_t) + BN * sizeof(float);
+    constexpr size_t kGrad = sizeof(GradLds<BM2, BN2>);
+    __shared__ __attribute__((aligned(16))) unsigned char smem[kBack > kGrad ? kBack : kGrad];
+    const int64_t nb = gx_back * gy_back, ng = gx * gy * gz, T = nb + ng;
+    const int64_t b = blockIdx.x;
+    // the ng gradient workgroups spread evenly over the grid: workgroup b is
+    // one when floor((b + 1) ng / T) steps up; it is then gradient workgroup
+    // floor(b ng / T), otherwise input-gradient workgroup b - floor(b ng / T)
+    const int64_t before = b * ng / T;
+    const bool is_grad = (b + 1) * ng / T > before;
+    const int back = is_grad ? -1 : (int)(b - before), grad = is_grad ? (int)before : -1;
+    if (back >= 0 && back < nb) {
+        uint16_t* Wz = reinterpret_cast<uint16_t*>(smem);
+        uint16_t* Wg = Wz + BN * WS;
+        float* bs = reinterpret_cast<float*>(Wg + BN * WS);
+        backward_tiles<BN>(ba, back % gx_back, back / gx_back, gx_back, Wz, Wg, bs);
+    } else if (grad >= 0 && grad < ng) {
+        grad_partials<BM2, BN2>(ga, grad % gx, (grad / gx) % gy, grad / (gx * gy),
+                                *reinterpret_cast<GradLds<BM2, BN2>*>(smem));
     }
 }
 
@@ -641,20 +717,29 @@ struct AdamArgs {
 // four consecutive groups, each summed in split order by one wave, the group
 // sums added in group order (independent of scheduling).  Layer l's partials
 // sit at part + S off[l] + s (off[l + 1] - off[l]) + (i - off[l]).  Without
-// Adam (a.w null) grad[i] = g; with it, Adam updates parameter i.
-// 64 parameters a workgroup of 256 threads.
-__global__ void __launch_bounds__(256) reduce_adam(const float* __restrict__ part, int S, LayerTable T,
-                                                   float* __restrict__ grad, AdamArgs a)
+// Adam (a.w null) grad[i] = g; with it, Adam updates parameter i.  A
+// workgroup of 256 threads takes 64 parameters of [i0, i1).
+struct ReduceArgs {
+    const float* part;
+    int S;
+    LayerTable T;
+    float* grad;
+    AdamArgs a;
+    int64_t i0, i1;
+};
+
+__device__ __forceinline__ void reduce_params(const ReduceArgs& r, int blk, float (&gs)[4][64])
 {
-    __shared__ float gs[4][64];
     const int col = threadIdx.x & 63, grp = threadIdx.x >> 6;
-    const int64_t i = (int64_t)blockIdx.x * 64 + col;
-    const int64_t total = T.off[T.layers];
-    const int l = i < total ? layer_of(T, i) : 0;
+    const int64_t i = r.i0 + (int64_t)blk * 64 + col;
+    const LayerTable& T = r.T;
+    const bool valid = i < r.i1;
+    const int l = valid ? layer_of(T, i) : 0;
+    const int S = r.S;
     float s = 0.f;
-    if (i < total) {
+    if (valid) {
         const int64_t wb = T.off[l + 1] - T.off[l];
-        const float* p = part + (int64_t)S * T.off[l] + (i - T.off[l]);
+        const float* p = r.part + (int64_t)S * T.off[l] + (i - T.off[l]);
         const int per = (S + 3) / 4, s0 = grp * per, s1 = min(S, s0 + per);
         // eight loads in flight, then added in split order
         for (int k = s0; k < s1; k += 8) {
@@ -668,10 +753,11 @@ __global__ void __launch_bounds__(256) reduce_adam(const float* __restrict__ par
     }
     gs[grp][col] = s;
     __syncthreads();
-    if (grp != 0 || i >= total) return;
+    if (grp != 0 || !valid) return;
     const float gi = ((gs[0][col] + gs[1][col]) + gs[2][col]) + gs[3][col];
+    const AdamArgs& a = r.a;
     if (!a.w) {
-        grad[i] = gi;
+        r.grad[i] = gi;
         return;
     }
     const float mi = 0.9f * a.m[i] + 0.1f * gi;
@@ -681,6 +767,12 @@ __global__ void __launch_bounds__(256) reduce_adam(const float* __restrict__ par
     const float wi = a.w[i] - a.lr_t * mi / (sqrtf(vi) + 1e-8f);
     a.w[i] = wi;
     write_bf16(T, l, i, wi, a.wbf, a.wbf_t);
+}
+
+__global__ void __launch_bounds__(256) reduce_adam(ReduceArgs r)
+{
+    __shared__ float gs[4][64];
+    reduce_params(r, blockIdx.x, gs);
 }
 
 // Copies a rows x cols block between a dense array and a padded one:

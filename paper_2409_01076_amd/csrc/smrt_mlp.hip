@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <limits>
 #include <new>
 #include <vector>
 
@@ -27,12 +28,14 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr int kMinSplitRows = 256;           // rows per weight-gradient row block, at least
 constexpr size_t kPartialBytes = 512u << 20; // budget of the row-block partials
-// Workgroups of a forward and of an input-gradient layer, each looping over
-// row tiles with the next tile's rows in flight.  At 65,536 rows a training
-// step measured the same with 512, 768 and 1024 forward groups and slower
-// with 256; 512 input-gradient groups (two a CU, by their LDS) beat 256 and 1024.
+// Workgroups of a forward layer and of the input-gradient part of a
+// backward grid, each looping over row tiles with the next tile's rows in
+// flight.  At 65,536 rows a training step measured the same with 512, 768
+// and 1024 forward groups and slower with 256.  The backward grid adds 256
+// weight-gradient blocks to its input-gradient groups; 256 of these (one of
+// each kind a CU) measured 0.179 ms a step, 384 0.194, 512 0.200, 128 0.200.
 constexpr int kForwardGroups = 512;
-constexpr int kBackwardGroups = 512;
+constexpr int kBackwardGroups = 256;
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct MlpLayout {
@@ -251,17 +254,37 @@ int splits_for(const MlpLayout& L, int n)
     return s;
 }
 
-int launch_weight_grad(hipStream_t s, const uint16_t* X, const uint16_t* dZ, int M, int N, int n, int splits, float* part)
+int launch_weight_grad(hipStream_t s, const smrt::mlp::GradArgs& a, int splits)
 {
     using namespace smrt::mlp;
-    const int bm = column_tile(M), bn = column_tile(N), rps = n / splits;
-    const int64_t stride = (int64_t)M * N + N;
-    dim3 grid(N / bn, M / bm, splits);
-    if (bm == 128 && bn == 128) weight_grad<128, 128><<<grid, ROW_THREADS, 0, s>>>(X, dZ, M, N, rps, part, stride);
-    else if (bm == 128) weight_grad<128, 64><<<grid, ROW_THREADS, 0, s>>>(X, dZ, M, N, rps, part, stride);
-    else if (bn == 128) weight_grad<64, 128><<<grid, ROW_THREADS, 0, s>>>(X, dZ, M, N, rps, part, stride);
-    else weight_grad<64, 64><<<grid, ROW_THREADS, 0, s>>>(X, dZ, M, N, rps, part, stride);
+    const int bm = column_tile(a.M), bn = column_tile(a.N);
+    dim3 grid(a.N / bn, a.M / bm, splits);
+    if (bm == 128 && bn == 128) weight_grad<128, 128><<<grid, ROW_THREADS, 0, s>>>(a);
+    else if (bm == 128) weight_grad<128, 64><<<grid, ROW_THREADS, 0, s>>>(a);
+    else if (bn == 128) weight_grad<64, 128><<<grid, ROW_THREADS, 0, s>>>(a);
+    else weight_grad<64, 64><<<grid, ROW_THREADS, 0, s>>>(a);
     return after_launch("weight_grad");
+}
+
+// Input gradient of layer l and its weight-gradient partials in one grid.
+int launch_backward_and_grad(hipStream_t s, const smrt::mlp::BackArgs& ba, int groups,
+                             const smrt::mlp::GradArgs& ga, int splits)
+{
+    using namespace smrt::mlp;
+    const int bn = column_tile(ba.K), bn2 = column_tile(ga.N); // ga.M == ba.K
+    const int gy_back = ba.K / bn, gx = ga.N / bn2, gy = ga.M / bn;
+    const int64_t total = (int64_t)groups * gy_back + (int64_t)gx * gy * splits;
+    if (total > std::numeric_limits<int>::max()) return fail(SMRT_EINVAL, "grid too large");
+    const dim3 grid((unsigned)total);
+    if (bn == 128 && bn2 == 128)
+        backward_and_grad<128, 128, 128><<<grid, ROW_THREADS, 0, s>>>(ba, groups, gy_back, ga, gx, gy, splits);
+    else if (bn == 128)
+        backward_and_grad<128, 128, 64><<<grid, ROW_THREADS, 0, s>>>(ba, groups, gy_back, ga, gx, gy, splits);
+    else if (bn2 == 128)
+        backward_and_grad<64, 64, 128><<<grid, ROW_THREADS, 0, s>>>(ba, groups, gy_back, ga, gx, gy, splits);
+    else
+        backward_and_grad<64, 64, 64><<<grid, ROW_THREADS, 0, s>>>(ba, groups, gy_back, ga, gx, gy, splits);
+    return after_launch("backward_and_grad");
 }
 
 // Backward pass after forward() with a target: the row-block partials of
@@ -282,28 +305,46 @@ int backward(smrt_mlp* m, int n, const smrt::mlp::AdamArgs* adam, double* loss)
     for (int l = L.layers - 1; l >= 0; --l) {
         const uint16_t* in = l == 0 ? m->x0() : m->a(l - 1);
         const int K = L.in[l], N = L.out[l];
-        rc = launch_weight_grad(s, in, dcur, K, N, n, splits, m->wpart() + (size_t)splits * L.w_off[l]);
-        if (rc) return rc;
-        if (l == 0) break;
-        // dZ_{l-1} = (dZ_l W_l^T) silu'(Z_{l-1}), Z_{l-1} = A_{l-2} W_{l-1} + b_{l-1}
-        const uint16_t* xp = l == 1 ? m->x0() : m->a(l - 2);
-        const int kp = L.in[l - 1];
-        uint16_t* dnext = m->dz(flip);
+        GradArgs ga;
+        ga.X = in;
+        ga.dZ = dcur;
+        ga.M = K;
+        ga.N = N;
+        ga.rps = n / splits;
+        ga.part = m->wpart() + (size_t)splits * L.w_off[l];
+        ga.split_stride = (int64_t)K * N + N;
+        if (l == 0) {
+            rc = launch_weight_grad(s, ga, splits);
+            if (rc) return rc;
+            break;
+        }
+        // dZ_{l-1} = (dZ_l W_l^T) silu'(Z_{l-1}), Z_{l-1} = A_{l-2} W_{l-1} + b_{l-1},
+        // beside the row-block partials of layer l's W and b gradient
+        BackArgs ba;
+        ba.dZ = dcur;
+        ba.N = N;
+        ba.W = m->wbf() + L.w_off[l];
+        ba.Xp = l == 1 ? m->x0() : m->a(l - 2);
+        ba.Kp = L.in[l - 1];
+        ba.Wpt = m->wbf_t() + L.w_off[l - 1];
+        ba.bp = m->params() + L.b_off[l - 1];
+        ba.K = K;
+        ba.tiles = tiles;
+        ba.dZout = m->dz(flip);
         flip ^= 1;
-        const int bn = column_tile(K);
-        dim3 grid(groups, K / bn);
-        const uint16_t* w = m->wbf() + L.w_off[l];
-        const uint16_t* wpt = m->wbf_t() + L.w_off[l - 1];
-        const float* bp = m->params() + L.b_off[l - 1];
-        if (bn == 128) layer_backward<128><<<grid, ROW_THREADS, 0, s>>>(dcur, N, w, xp, kp, wpt, bp, K, tiles, dnext);
-        else layer_backward<64><<<grid, ROW_THREADS, 0, s>>>(dcur, N, w, xp, kp, wpt, bp, K, tiles, dnext);
-        rc = after_launch("layer_backward");
+        rc = launch_backward_and_grad(s, ba, groups, ga, splits);
         if (rc) return rc;
-        dcur = dnext;
+        dcur = ba.dZout;
     }
-    const AdamArgs none;
-    reduce_adam<<<(int)((L.padded_params + 63) / 64), 256, 0, s>>>(m->wpart(), splits, L.table, m->grad(),
-                                                                   adam ? *adam : none);
+    ReduceArgs r;
+    r.part = m->wpart();
+    r.S = splits;
+    r.T = L.table;
+    r.grad = m->grad();
+    if (adam) r.a = *adam;
+    r.i0 = 0;
+    r.i1 = (int64_t)L.padded_params;
+    reduce_adam<<<(int)((r.i1 + 63) / 64), 256, 0, s>>>(r);
     rc = after_launch("reduce_adam");
     if (rc) return rc;
     if (loss) {
