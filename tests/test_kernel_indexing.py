@@ -347,3 +347,23 @@ def test_moment_kernel_indexing(mom_ty, e_moment, e_amp, boundary, nx, ny):
                     cell = (lx - EX[a], ly - EY[a])
                     assert 0 <= cell[0] < fx and 0 <= cell[1] < fy
                     assert staged[cell] == ((sx % nx, sy % ny) if per else (sx, sy))
+
+
+@pytest.mark.parametrize("nb,ng", [(256, 256), (512, 256), (256, 64), (1, 1), (7, 300), (300, 7), (1024, 1)])
+def test_backward_and_grad_roles_cover_each_workgroup_once(nb, ng):
+    """backward_and_grad's role spread over a grid of T = nb + ng workgroups:
+    workgroup b is a gradient block when floor((b + 1) ng / T) steps up, block
+    floor(b ng / T), else input-gradient workgroup b - floor(b ng / T).  Every
+    index of each role is taken exactly once, and the gradient blocks are
+    spread evenly (at most one more in any prefix than its share)."""
+    T = nb + ng
+    b = np.arange(T, dtype=np.int64)
+    before = b * ng // T
+    is_grad = (b + 1) * ng // T > before
+    back = (b - before)[~is_grad]
+    grad = before[is_grad]
+    assert np.array_equal(np.sort(back), np.arange(nb))
+    assert np.array_equal(np.sort(grad), np.arange(ng))
+    prefix = np.cumsum(is_grad)
+    share = (b + 1) * ng / T
+    assert np.all(np.abs(prefix - share) < 1.0)
