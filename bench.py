@@ -531,22 +531,31 @@ def mlp_step(args, rows=65536):
     pts = torch.from_numpy(rng.uniform(0, 1, size=(rows, 3)).astype(np.float32)).to("cuda:0")
     tgt = torch.from_numpy(rng.normal(0, 0.5, size=(rows, 3)).astype(np.float32)).to("cuda:0")
     ws = W.WarmStart(fourier=16, width=128, layers=5, batch=rows)
-    for _ in range(max(1, args.warmup)):
-        ws.net.train_step(pts, tgt, 1e-3)
     stream = ws.net.stream
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        ws.net.train_step(pts, tgt, 1e-3)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
+
+    def timed():
+        for _ in range(max(1, args.warmup)):
+            ws.net.train_step(pts, tgt, 1e-3)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            ws.net.train_step(pts, tgt, 1e-3)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
+    fused = ws.net.fused_forward
+    ms = timed()
+    # the same step with one forward launch per layer
+    ws.net.fused_forward = False
+    ms_layers = timed()
     ws.close()
     flops = 6.0 * rows * (64 * 128 + 3 * 128 * 128 + 128 * 64)  # forward + two backward products, padded sizes
     return {"workload": "warm-start network training step: %d rows, 5 weight layers of width 128, "
                         "16 Fourier features, bf16 matrix cores, Adam" % rows,
-            "steps": args.steps, "ms_per_step": round(ms, 4),
+            "steps": args.steps, "ms_per_step": round(ms, 4), "fused_forward": fused,
+            "ms_per_step_forward_per_layer": round(ms_layers, 4),
             "tflops_padded": round(flops / (ms * 1e-3) / 1e12, 1)}
 
 

@@ -423,6 +423,21 @@ int smrt_mlp_get_params(smrt_mlp* m, float* params);
 /* out[n][outputs] (device FP32) for points[n][3] (device FP32).  Asynchronous. */
 int smrt_mlp_forward(smrt_mlp* m, const float* points, int32_t n, float* out);
 
+/* Kernels of the forward pass (also inside smrt_mlp_gradient and
+ * smrt_mlp_train_step).  enable != 0 (the default): one launch for every
+ * layer where the network fits the matrix cores' LDS-resident form (input
+ * features padded to 64 or 128 columns, width 64 or 128, at most 8 layers,
+ * transposed bf16 weights of at most 140,288 bytes: the default 5-layer,
+ * width-128 network with up to 30 frequencies); enable == 0: one launch per
+ * layer.  Both produce bitwise the same activations, outputs and gradients
+ * (the squared-error loss is summed in another block order).  Returns
+ * SMRT_OK or SMRT_EINVAL for a NULL network. */
+int smrt_mlp_set_fused_forward(smrt_mlp* m, int32_t enable);
+
+/* 1 if the forward pass runs as one launch (enabled and the network fits),
+ * 0 if it runs layer by layer, SMRT_EINVAL for a NULL network. */
+int smrt_mlp_uses_fused_forward(const smrt_mlp* m);
+
 /* Gradient of the mean squared error sum (y - target)^2 / (n outputs) with
  * respect to the parameters, into grad (device, dense layout); target is
  * [n][outputs] (device FP32).  loss (host, may be NULL) receives the error

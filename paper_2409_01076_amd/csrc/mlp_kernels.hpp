@@ -377,6 +377,182 @@ __global__ void __launch_bounds__(ROW_THREADS, 3) layer_forward(const uint16_t* 
     }
 }
 
+// The whole forward pass in one launch, for networks whose transposed bf16
+// weights fit in LDS together (input width K0, hidden width H, 64 output
+// columns).  Each wave takes 16 rows at a time through every layer: the
+// layer's sums come from the same operands in the same MFMA order as
+// layer_forward's (so the activations, outputs and loss terms are bitwise
+// theirs), and the bf16 activations go both to HBM (the backward pass reads
+// them) and, through lane permutes, into the MFMA operand layout of the next
+// layer: the sums leave lane (r, q) four consecutive columns of row r, the
+// next product wants eight.  Every layer's W^T is staged once per workgroup
+// (row stride K + 8 elements: the 16 rows one operand read touches land on
+// distinct groups of four banks for K = 64 and 128); with the weights filling
+// the LDS, a workgroup of 8 waves per CU keeps two waves on every SIMD.  Rows
+// of the wave's next 16-row block are in flight while the current one runs.
+// The loss partial of workgroup b goes to o.loss[b].
+constexpr int kFusedMaxLayers = 8;
+constexpr int kFusedWeightElems = 70144; // 140,288 bytes of LDS
+constexpr int kFusedBiasFloats = 1024;
+constexpr int FUSED_THREADS = 512;
+struct FusedArgs {
+    const uint16_t* X0;                      // [rows][K0] input features
+    int layers;                              // hidden layers + 1
+    const uint16_t* wt[kFusedMaxLayers];     // W_l^T, [N_l][K_l] bf16
+    const float* bias[kFusedMaxLayers];      // b_l, N_l floats
+    uint16_t* act[kFusedMaxLayers];          // A_l, [rows][H] bf16, hidden layers
+    int blocks;                              // rows / 16
+    FwdOut o;                                // output layer (N = 64)
+};
+
+// LDS elements of the packed transposed weights of such a network
+constexpr int fused_weight_elems(int k0, int h, int layers)
+{
+    return h * (k0 + 8) + (layers - 2) * h * (h + 8) + 64 * (h + 8);
+}
+
+// acc[j] += the 16 x 16 block of X Ws^T (staged rows 16 j .. 16 j + 15,
+// row stride LD) for the K columns held in xf; the operand order of
+// rows_times_staged.
+template <int FJ, int K, int LD>
+__device__ __forceinline__ void rows_times_resident(f32x4 (&acc)[FJ], const bf16x8 (&xf)[KC / 32],
+                                                    const uint16_t* Ws)
+{
+    const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+#pragma unroll
+    for (int kk = 0; kk < K / 32; ++kk) {
+#pragma unroll
+        for (int j = 0; j < FJ; ++j) {
+            const bf16x8 w = *reinterpret_cast<const bf16x8*>(Ws + (16 * j + r) * LD + kk * 32 + 8 * q);
+            acc[j] = mfma(w, xf[kk], acc[j]);
+        }
+    }
+}
+
+// Lane (r, q) holds pk[j] = bf16 columns 16 j + 4 q .. + 3 of row r; returns
+// in xf[kk] columns 32 kk + 8 q .. + 7: the first four from lane group
+// 2q mod 4, the next four from 2q + 1 mod 4, of column block j = 2 kk + q / 2.
+template <int FJ>
+__device__ __forceinline__ void regroup_rows(const uint2 (&pk)[FJ], bf16x8 (&xf)[KC / 32])
+{
+    const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+    const int src_a = (r + 16 * ((2 * q) & 3)) * 4, src_b = (r + 16 * ((2 * q + 1) & 3)) * 4;
+    const bool upper = q >= 2;
+    const auto take = [&](int src, uint32_t lo, uint32_t hi) {
+        const uint32_t a = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)lo);
+        const uint32_t b = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)hi);
+        return upper ? b : a;
+    };
+#pragma unroll
+    for (int kk = 0; kk < FJ / 2; ++kk) {
+        const uint2 e = pk[2 * kk], o = pk[2 * kk + 1];
+        const u32x4 v{take(src_a, e.x, o.x), take(src_a, e.y, o.y), take(src_b, e.x, o.x), take(src_b, e.y, o.y)};
+        xf[kk] = __builtin_bit_cast(bf16x8, v);
+    }
+}
+
+template <int K0, int H, int MODE>
+__global__ void __launch_bounds__(FUSED_THREADS, 1) forward_fused(FusedArgs a)
+{
+    static_assert(K0 % 64 == 0 && K0 <= KC && (H == 64 || H == 128), "fused forward shapes");
+    constexpr int FJ = H / 16, WAVES = FUSED_THREADS / 64;
+    __shared__ __attribute__((aligned(16))) uint16_t Ws[kFusedWeightElems];
+    __shared__ __attribute__((aligned(16))) float bs[kFusedBiasFloats];
+    __shared__ double lds[WAVES];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+    const int L = a.layers;
+    // stage every layer's W^T and bias
+    {
+        int off = 0;
+        for (int l = 0; l < L; ++l) {
+            const int K = l == 0 ? K0 : H, N = l == L - 1 ? 64 : H, cpr = K >> 3;
+            for (int c = threadIdx.x; c < N * cpr; c += FUSED_THREADS) {
+                const int row = c / cpr, k8 = (c - row * cpr) * 8;
+                *reinterpret_cast<u32x4*>(Ws + off + row * (K + 8) + k8) =
+                    *reinterpret_cast<const u32x4*>(a.wt[l] + (int64_t)row * K + k8);
+            }
+            for (int c = threadIdx.x; c < N; c += FUSED_THREADS) bs[l * 128 + c] = a.bias[l][c];
+            off += N * (K + 8);
+        }
+    }
+    __syncthreads();
+    double lsum = 0.0;
+    bf16x8 xf[KC / 32], xn[KC / 32];
+    int b = blockIdx.x * WAVES + wave;
+    const int stride = gridDim.x * WAVES;
+    if (b < a.blocks) load_rows(xf, a.X0, K0, b * 16, 0, K0);
+    for (; b < a.blocks; b += stride) {
+        if (b + stride < a.blocks) load_rows(xn, a.X0, K0, (b + stride) * 16, 0, K0);
+        const int64_t m = (int64_t)b * 16 + r;
+        const uint16_t* W = Ws;
+        for (int l = 0; l < L - 1; ++l) {
+            f32x4 acc[FJ];
+#pragma unroll
+            for (int j = 0; j < FJ; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+            if (l == 0) {
+                rows_times_resident<FJ, K0, K0 + 8>(acc, xf, W);
+                W += H * (K0 + 8);
+            } else {
+                rows_times_resident<FJ, H, H + 8>(acc, xf, W);
+                W += H * (H + 8);
+            }
+            uint16_t* act = a.act[l];
+            uint2 pk[FJ];
+#pragma unroll
+            for (int j = 0; j < FJ; ++j) {
+                const int n = 16 * j + 4 * q;
+                const f32x4 b4 = *reinterpret_cast<const f32x4*>(&bs[l * 128 + n]);
+                float h[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float v = acc[j][i] + b4[i];
+                    h[i] = v * sigmoid(v);
+                }
+                pk[j] = make_uint2(pack_bf16(h[0], h[1]), pack_bf16(h[2], h[3]));
+                *reinterpret_cast<uint2*>(act + m * H + n) = pk[j];
+            }
+            regroup_rows<FJ>(pk, xf);
+        }
+        f32x4 acc[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        rows_times_resident<4, H, H + 8>(acc, xf, W);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int n = 16 * j + 4 * q;
+            const f32x4 b4 = *reinterpret_cast<const f32x4*>(&bs[(L - 1) * 128 + n]);
+            float h[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float v = acc[j][i] + b4[i];
+                h[i] = 0.f;
+                if (n + i < a.o.keep) {
+                    a.o.y[m * a.o.keep + n + i] = v;
+                    if constexpr (MODE == FWD_OUT_MSE) {
+                        const float e = v - a.o.target[m * a.o.keep + n + i];
+                        lsum += (double)e * e;
+                        h[i] = a.o.scale * e;
+                    }
+                }
+            }
+            if constexpr (MODE == FWD_OUT_MSE) store_bf16x4(a.o.dy + m * 64 + n, h);
+        }
+#pragma unroll
+        for (int kk = 0; kk < KC / 32; ++kk) xf[kk] = xn[kk];
+    }
+    if constexpr (MODE == FWD_OUT_MSE) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
+        if (lane == 0) lds[wave] = lsum;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int w = 0; w < WAVES; ++w) t += lds[w];
+            a.o.loss[blockIdx.x] = t;
+        }
+    }
+}
+
 // Input gradient of layer l over `tiles` row tiles, output columns
 // [BN blockIdx.y, BN (blockIdx.y + 1)) of K:
 //   dZout[m][n] = bf16(g silu'(z)),  g = (dZ W_l^T)[m][n],

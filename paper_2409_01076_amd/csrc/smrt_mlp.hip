@@ -36,6 +36,8 @@ constexpr size_t kPartialBytes = 512u << 20; // budget of the row-block partials
 // each kind a CU) measured 0.179 ms a step, 384 0.194, 512 0.200, 128 0.200.
 constexpr int kForwardGroups = 512;
 constexpr int kBackwardGroups = 256;
+// The one-launch forward pass: one workgroup of 8 waves a CU (its weights fill the LDS).
+constexpr int kFusedGroups = 256;
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct MlpLayout {
@@ -142,6 +144,7 @@ struct smrt_mlp {
     bool owns_ws = false;
     int64_t adam_steps = 0;
     int loss_parts = 0; // squared-error partials written by the last forward pass with a target
+    bool fused = true;  // one launch for the whole forward pass where the network fits
     bool has_params = false;
     std::vector<double> loss_host;
 
@@ -198,6 +201,54 @@ int check_batch(const smrt_mlp* m, int32_t n)
 // Output-column tile of the row-tile kernels: 128 where the width allows.
 int column_tile(int n) { return n % 128 == 0 ? 128 : 64; }
 
+// Whether the network's transposed weights fit the one-launch forward pass.
+bool fused_fits(const MlpLayout& L)
+{
+    using namespace smrt::mlp;
+    return (L.k0 == 64 || L.k0 == 128) && (L.width == 64 || L.width == 128) && L.layers <= kFusedMaxLayers &&
+           fused_weight_elems(L.k0, L.width, L.layers) <= kFusedWeightElems;
+}
+
+int forward_fused_launch(smrt_mlp* m, int n, float* out, const float* target)
+{
+    using namespace smrt::mlp;
+    const MlpLayout& L = m->L;
+    FusedArgs a{};
+    a.X0 = m->x0();
+    a.layers = L.layers;
+    for (int l = 0; l < L.layers; ++l) {
+        a.wt[l] = m->wbf_t() + L.w_off[l];
+        a.bias[l] = m->params() + L.b_off[l];
+        if (l < L.layers - 1) a.act[l] = m->a(l);
+    }
+    a.blocks = n / 16;
+    a.o.y = out;
+    a.o.keep = L.outputs;
+    const int waves = FUSED_THREADS / 64;
+    const int groups = std::min(kFusedGroups, (a.blocks + waves - 1) / waves);
+    if (target) {
+        a.o.target = target;
+        a.o.dy = m->dy();
+        a.o.scale = 2.0f / ((float)n * L.outputs);
+        a.o.loss = m->loss_part();
+        m->loss_parts = groups;
+    }
+    const int mse = target != nullptr;
+    hipStream_t s = m->stream;
+#define SMRT_FUSED(K0, H)                                                                    \
+    if (L.k0 == K0 && L.width == H) {                                                        \
+        if (mse) forward_fused<K0, H, FWD_OUT_MSE><<<groups, FUSED_THREADS, 0, s>>>(a);        \
+        else forward_fused<K0, H, FWD_OUT><<<groups, FUSED_THREADS, 0, s>>>(a);                \
+        return after_launch("forward_fused");                                                \
+    }
+    SMRT_FUSED(64, 128)
+    SMRT_FUSED(64, 64)
+    SMRT_FUSED(128, 128)
+    SMRT_FUSED(128, 64)
+#undef SMRT_FUSED
+    return fail(SMRT_ESTATE, "no fused forward kernel for %d features, width %d", L.k0, L.width);
+}
+
 // Forward pass over n rows of points.  Hidden activations go to m->a(l); the
 // output layer writes `out` ([n][outputs]) and, given a target, also the MSE
 // gradient m->dy() and the squared-error partials m->loss_part().
@@ -209,6 +260,7 @@ int forward(smrt_mlp* m, const float* pts, int n, float* out, const float* targe
     features<<<n / 64, 256, 0, s>>>(pts, m->fourier(), L.nf, n, L.k0, m->x0());
     int rc = after_launch("features");
     if (rc) return rc;
+    if (m->fused && fused_fits(L)) return forward_fused_launch(m, n, out, target);
     const int tiles = n / RT;
     const int groups = std::min(tiles, kForwardGroups);
     for (int l = 0; l < L.layers; ++l) {
@@ -468,6 +520,19 @@ int smrt_mlp_forward(smrt_mlp* m, const float* points, int32_t n, float* out)
     int rc = check_batch(m, n);
     if (rc) return rc;
     return forward(m, points, n, out, nullptr);
+}
+
+int smrt_mlp_set_fused_forward(smrt_mlp* m, int32_t enable)
+{
+    if (!m) return fail(SMRT_EINVAL, "network is NULL");
+    m->fused = enable != 0;
+    return SMRT_OK;
+}
+
+int smrt_mlp_uses_fused_forward(const smrt_mlp* m)
+{
+    if (!m) return fail(SMRT_EINVAL, "network is NULL");
+    return m->fused && fused_fits(m->L) ? 1 : 0;
 }
 
 int smrt_mlp_gradient(smrt_mlp* m, const float* points, const float* target, int32_t n, float* grad,

@@ -32,7 +32,7 @@ EXPORTED = (
     "smrt_batch_running", "smrt_batch_steps_per_launch", "smrt_batch_set_launch", "smrt_batch_destroy",
     "smrt_mlp_param_count", "smrt_mlp_workspace_bytes", "smrt_mlp_create", "smrt_mlp_set_params",
     "smrt_mlp_get_params", "smrt_mlp_forward", "smrt_mlp_gradient", "smrt_mlp_train_step",
-    "smrt_mlp_destroy", "smrt_gemm_bf16",
+    "smrt_mlp_destroy", "smrt_mlp_set_fused_forward", "smrt_mlp_uses_fused_forward", "smrt_gemm_bf16",
 )
 RUNNING, STEADY, UNSTABLE = 0, 1, 2
 
@@ -140,6 +140,8 @@ def load():
         "smrt_mlp_gradient": (ctypes.c_int, [vp, vp, vp, i32, vp, dp]),
         "smrt_mlp_train_step": (ctypes.c_int, [vp, vp, vp, i32, ctypes.c_float, dp]),
         "smrt_mlp_destroy": (None, [vp]),
+        "smrt_mlp_set_fused_forward": (ctypes.c_int, [vp, i32]),
+        "smrt_mlp_uses_fused_forward": (ctypes.c_int, [vp]),
         "smrt_gemm_bf16": (ctypes.c_int, [vp, vp, vp, i32, i32, i32, i32, i32, i32, i32, i32, i32, vp]),
     }
     for name, (res, args) in sig.items():
@@ -579,6 +581,17 @@ class MLP:
         with _caller_order(self.stream, self.device):
             _check(load().smrt_mlp_get_params(self._ctx, _ptr(out)))
         return out
+
+    @property
+    def fused_forward(self):
+        """True when the forward pass runs as one launch (smrt_mlp_set_fused_forward)."""
+        rc = load().smrt_mlp_uses_fused_forward(self._ctx)
+        _check(min(rc, 0))
+        return rc == 1
+
+    @fused_forward.setter
+    def fused_forward(self, enable):
+        _check(load().smrt_mlp_set_fused_forward(self._ctx, int(bool(enable))))
 
     def forward(self, points, out=None):
         n = points.shape[0]

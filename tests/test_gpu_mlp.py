@@ -122,6 +122,47 @@ def test_gradient_other_shapes(smrt, fourier, width, layers, outputs, n):
     assert abs(loss - want_loss) <= loss_tol + 1e-12 * want_loss
 
 
+@pytest.mark.parametrize("fourier,width,layers,outputs,n", [
+    (16, 128, 5, 3, 65536),  # the warm-start network: 35 features padded to 64, LDS full
+    (16, 128, 5, 3, 320),    # 20 blocks of 16 rows: 5 workgroups, one block a wave
+    (30, 128, 5, 3, 1024),   # 63 features, the widest first layer that still fits
+    (4, 64, 3, 2, 512),      # width 64
+    (40, 64, 3, 3, 1024),    # 83 features padded to 128, width 64
+    (40, 128, 4, 1, 2048),   # 128 features, width 128, four layers
+])
+def test_fused_forward_bitwise_equals_per_layer(smrt, fourier, width, layers, outputs, n):
+    """The one-launch forward pass against one launch per layer: outputs and
+    every gradient entry bitwise equal (same operands, same MFMA order), the
+    loss equal up to the order of its FP64 block sums."""
+    rng = np.random.default_rng(fourier * 7 + width + layers + n)
+    dims, params, B = make_net(rng, fourier=fourier, width=width, layers=layers, outputs=outputs)
+    params, B = params.astype(np.float32), B.astype(np.float32)
+    pts = torch.tensor(rng.uniform(0, 1, size=(n, 3)).astype(np.float32), device="cuda:0")
+    tgt = torch.tensor(rng.normal(0, 0.5, size=(n, outputs)).astype(np.float32), device="cuda:0")
+    res = {}
+    with smrt.MLP(fourier=fourier, width=width, layers=layers, outputs=outputs, max_batch=n) as net:
+        net.set_params(torch.tensor(params, device="cuda:0"), torch.tensor(B, device="cuda:0"))
+        assert net.fused_forward
+        for fused in (True, False):
+            net.fused_forward = fused
+            assert net.fused_forward == fused
+            y = net.forward(pts).clone()
+            loss, g = net.gradient(pts, tgt)
+            res[fused] = (y, loss, g.clone())
+    print("n %d: loss fused %.17g, per layer %.17g" % (n, res[True][1], res[False][1]))
+    assert torch.equal(res[True][0], res[False][0])
+    assert torch.equal(res[True][2], res[False][2])
+    assert abs(res[True][1] - res[False][1]) <= 1e-12 * abs(res[False][1])
+
+
+def test_fused_forward_only_where_it_fits(smrt):
+    """Width 192 or 256, or a 128-feature input with four 128-wide hidden
+    layers, exceed the LDS-resident form: those networks run layer by layer."""
+    for fourier, width, layers in [(8, 192, 2), (40, 256, 3), (40, 128, 5)]:
+        with smrt.MLP(fourier=fourier, width=width, layers=layers, outputs=3, max_batch=256) as net:
+            assert not net.fused_forward
+
+
 def to_bf16_bits(a):
     """float array of bf16-exact values -> int16 tensor of their bit patterns."""
     u = np.ascontiguousarray(a, np.float32).view(np.uint32)
