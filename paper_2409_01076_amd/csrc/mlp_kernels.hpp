@@ -388,13 +388,14 @@ __global__ void __launch_bounds__(ROW_THREADS, 3) layer_forward(const uint16_t* 
 // next product wants eight.  Every layer's W^T is staged once per workgroup
 // (row stride K + 8 elements: the 16 rows one operand read touches land on
 // distinct groups of four banks for K = 64 and 128); with the weights filling
-// the LDS, a workgroup of 8 waves per CU keeps two waves on every SIMD.  Rows
-// of the wave's next 16-row block are in flight while the current one runs.
+// the LDS, a workgroup of 12 waves per CU keeps three waves on every SIMD.
+// Rows of the wave's next 16-row block are in flight while the current one
+// runs.
 // The loss partial of workgroup b goes to o.loss[b].
 constexpr int kFusedMaxLayers = 8;
 constexpr int kFusedWeightElems = 70144; // 140,288 bytes of LDS
 constexpr int kFusedBiasFloats = 1024;
-constexpr int FUSED_THREADS = 512;
+constexpr int FUSED_THREADS = 768;
 struct FusedArgs {
     const uint16_t* X0;                      // [rows][K0] input features
     int layers;                              // hidden layers + 1
@@ -478,8 +479,10 @@ __global__ void __launch_bounds__(FUSED_THREADS, 1) forward_fused(FusedArgs a)
     __syncthreads();
     double lsum = 0.0;
     bf16x8 xf[KC / 32], xn[KC / 32];
-    int b = blockIdx.x * WAVES + wave;
+    // blocks blockIdx.x + gridDim.x t, t = wave, wave + WAVES, ...: every
+    // workgroup gets the same number of blocks, spread over its SIMDs
     const int stride = gridDim.x * WAVES;
+    int b = blockIdx.x + gridDim.x * wave;
     if (b < a.blocks) load_rows(xf, a.X0, K0, b * 16, 0, K0);
     for (; b < a.blocks; b += stride) {
         if (b + stride < a.blocks) load_rows(xn, a.X0, K0, (b + stride) * 16, 0, K0);
@@ -890,11 +893,14 @@ struct AdamArgs {
 };
 
 // g[i] = sum over the S row-block partials of parameter i: the splits in
-// four consecutive groups, each summed in split order by one wave, the group
-// sums added in group order (independent of scheduling).  Layer l's partials
-// sit at part + S off[l] + s (off[l + 1] - off[l]) + (i - off[l]).  Without
-// Adam (a.w null) grad[i] = g; with it, Adam updates parameter i.  A
-// workgroup of 256 threads takes 64 parameters of [i0, i1).
+// sixteen consecutive groups, each summed in split order, the group sums
+// added in group order (independent of scheduling).  Layer l's partials sit
+// at part + S off[l] + s (off[l + 1] - off[l]) + (i - off[l]).  Without Adam
+// (a.w null) grad[i] = g; with it, Adam updates parameter i.  A workgroup of
+// 256 threads takes 64 parameters of [i0, i1) (i0, i1 and every layer's
+// offset multiples of 64): 16 lanes cover them with 16-byte loads, so each
+// wave holds four groups and every load instruction reads four partials.
+constexpr int RED_PARAMS = 64, RED_GROUPS = 16, REDUCE_THREADS = 256;
 struct ReduceArgs {
     const float* part;
     int S;
@@ -904,33 +910,39 @@ struct ReduceArgs {
     int64_t i0, i1;
 };
 
-__device__ __forceinline__ void reduce_params(const ReduceArgs& r, int blk, float (&gs)[4][64])
+__global__ void __launch_bounds__(REDUCE_THREADS) reduce_adam(ReduceArgs r)
 {
-    const int col = threadIdx.x & 63, grp = threadIdx.x >> 6;
-    const int64_t i = r.i0 + (int64_t)blk * 64 + col;
+    __shared__ __attribute__((aligned(16))) float gs[RED_GROUPS][RED_PARAMS];
+    const int c = threadIdx.x & 15, grp = threadIdx.x >> 4;
     const LayerTable& T = r.T;
-    const bool valid = i < r.i1;
-    const int l = valid ? layer_of(T, i) : 0;
     const int S = r.S;
-    float s = 0.f;
-    if (valid) {
+    const int64_t base = r.i0 + (int64_t)blockIdx.x * RED_PARAMS;
+    const int64_t i4 = base + 4 * c;
+    f32x4 s{0.f, 0.f, 0.f, 0.f};
+    if (i4 < r.i1) {
+        const int l = layer_of(T, i4);
         const int64_t wb = T.off[l + 1] - T.off[l];
-        const float* p = r.part + (int64_t)S * T.off[l] + (i - T.off[l]);
-        const int per = (S + 3) / 4, s0 = grp * per, s1 = min(S, s0 + per);
+        const float* p = r.part + (int64_t)S * T.off[l] + (i4 - T.off[l]);
+        const int per = (S + RED_GROUPS - 1) / RED_GROUPS, s0 = grp * per, s1 = min(S, s0 + per);
         // eight loads in flight, then added in split order
         for (int k = s0; k < s1; k += 8) {
-            float v[8];
+            f32x4 v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = k + u < s1 ? p[(int64_t)(k + u) * wb] : 0.f;
+            for (int u = 0; u < 8; ++u)
+                v[u] = k + u < s1 ? *reinterpret_cast<const f32x4*>(p + (int64_t)(k + u) * wb) : f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int u = 0; u < 8; ++u)
                 if (k + u < s1) s += v[u];
         }
     }
-    gs[grp][col] = s;
+    *reinterpret_cast<f32x4*>(&gs[grp][4 * c]) = s;
     __syncthreads();
-    if (grp != 0 || !valid) return;
-    const float gi = ((gs[0][col] + gs[1][col]) + gs[2][col]) + gs[3][col];
+    const int t = threadIdx.x;
+    const int64_t i = base + t;
+    if (t >= RED_PARAMS || i >= r.i1) return;
+    float gi = gs[0][t];
+#pragma unroll
+    for (int g = 1; g < RED_GROUPS; ++g) gi += gs[g][t];
     const AdamArgs& a = r.a;
     if (!a.w) {
         r.grad[i] = gi;
@@ -942,13 +954,7 @@ __device__ __forceinline__ void reduce_params(const ReduceArgs& r, int blk, floa
     a.v[i] = vi;
     const float wi = a.w[i] - a.lr_t * mi / (sqrtf(vi) + 1e-8f);
     a.w[i] = wi;
-    write_bf16(T, l, i, wi, a.wbf, a.wbf_t);
-}
-
-__global__ void __launch_bounds__(256) reduce_adam(ReduceArgs r)
-{
-    __shared__ float gs[4][64];
-    reduce_params(r, blockIdx.x, gs);
+    write_bf16(T, layer_of(T, i), i, wi, a.wbf, a.wbf_t);
 }
 
 // Copies a rows x cols block between a dense array and a padded one:

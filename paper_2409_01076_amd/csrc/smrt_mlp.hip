@@ -36,7 +36,7 @@ constexpr size_t kPartialBytes = 512u << 20; // budget of the row-block partials
 // each kind a CU) measured 0.179 ms a step, 384 0.194, 512 0.200, 128 0.200.
 constexpr int kForwardGroups = 512;
 constexpr int kBackwardGroups = 256;
-// The one-launch forward pass: one workgroup of 8 waves a CU (its weights fill the LDS).
+// The one-launch forward pass: one workgroup of 12 waves a CU (its weights fill the LDS).
 constexpr int kFusedGroups = 256;
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -396,7 +396,7 @@ int backward(smrt_mlp* m, int n, const smrt::mlp::AdamArgs* adam, double* loss)
     if (adam) r.a = *adam;
     r.i0 = 0;
     r.i1 = (int64_t)L.padded_params;
-    reduce_adam<<<(int)((r.i1 + 63) / 64), 256, 0, s>>>(r);
+    reduce_adam<<<(int)((r.i1 + RED_PARAMS - 1) / RED_PARAMS), REDUCE_THREADS, 0, s>>>(r);
     rc = after_launch("reduce_adam");
     if (rc) return rc;
     if (loss) {

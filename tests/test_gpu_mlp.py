@@ -41,12 +41,13 @@ def gradient_depth(n, max_splits=256):
     (weight and bias gradients).  The library splits the rows into S blocks
     (S = max_splits, halved until S divides n into blocks of at least 256
     rows, a multiple of 64 each), accumulates each block on the matrix cores
-    (n / S additions), then sums the S partials in one pass in four
-    consecutive groups (S / 4 additions, then 3 to join the groups)."""
+    (n / S additions), then sums the S partials in one pass in sixteen
+    consecutive groups (at most S / 16 + 1 additions, then 15 to join the
+    groups)."""
     sp = max_splits
     while sp > 1 and (n % (64 * sp) or n // sp < 256):
         sp //= 2
-    return n // sp + sp // 4 + 4
+    return n // sp + sp // 16 + 16
 
 
 def test_forward_matches_oracle(smrt):
