@@ -79,8 +79,10 @@ typedef enum smrt_dtype {
     SMRT_F32X = 4,/* storage only: binary32 deviations, FP64 arithmetic: each
                      collision is computed in FP64 and rounded once per stored
                      value, so the only FP32 error is the storage's own
-                     (binary32 collision arithmetic biases the momentum
-                     balance of a slowly converging cavity) */
+                     (about 5x below SMRT_F32's on a slowly converging
+                     cavity; SMRT_F32 takes 1/12 of the diagonal links' odd
+                     equilibrium terms as a pair of binary32 constants, since
+                     one rounded constant biases every node alike) */
     /* Moment storage (SmrtLBM only; cavity or periodic; one time step per
      * launch).  Eq. (SmrtLBM-1) makes the post-collision populations a
      * function of five numbers per node, f*_a = f^eq_a(rho, u) + (-1)^a g_grp(a)
