@@ -626,14 +626,21 @@ __device__ __forceinline__ void pull_lds(const typename Storage<T>::M (&m)[9][FY
 #pragma unroll
     for (int a = 0; a < 9; ++a) d[a] = (C)own[a * PL - EY[a] * FX - EX[a]];
     if constexpr (BC == CAVITY && !INNER) {
-        // only lanes on the lattice's outer ring have sources beyond a wall
-        if ((x == 0) | (x == g.nx - 1) | (y == 0) | (y == g.ny - 1)) {
+        // only lanes on the lattice's outer ring have sources beyond a wall:
+        // x - e_x < 0 only at x = 0 with e_x = 1, x - e_x = nx only at
+        // x = nx - 1 with e_x = -1, likewise in y; the lid row y = ny feeds
+        // the links with e_y = -1 at y = ny - 1, corners included
+        const bool wl = x == 0, wr = x == g.nx - 1, wb = y == 0, wt = y == g.ny - 1;
+        if (wl | wr | wb | wt) {
 #pragma unroll
             for (int a = 1; a < 9; ++a) {
-                const int sx = x - EX[a], sy = y - EY[a];
-                const bool inside = (unsigned)sx < (unsigned)g.nx && (unsigned)sy < (unsigned)g.ny;
+                const bool bx = EX[a] > 0 ? wl : (EX[a] < 0 ? wr : false);
+                const bool by = EY[a] > 0 ? wb : (EY[a] < 0 ? wt : false);
                 const C back = (C)own[OPP[a] * PL];
-                d[a] = inside ? d[a] : ((sy == g.ny) ? back + C(EX[a]) * lid : back);
+                if (EY[a] < 0) // folded once the loop is unrolled
+                    d[a] = (bx | by) ? (wt ? back + C(EX[a]) * lid : back) : d[a];
+                else
+                    d[a] = (bx | by) ? back : d[a];
             }
         }
     }
