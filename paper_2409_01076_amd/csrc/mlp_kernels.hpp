@@ -188,8 +188,10 @@ __global__ void __launch_bounds__(256) features(const float* __restrict__ p, con
     const float x = p[row * 3 + 0], y = p[row * 3 + 1], s = p[row * 3 + 2];
     for (int j = part; j < nf; j += 4) {
         const float arg = 6.283185307179586f * (Bf[j * 3 + 0] * x + Bf[j * 3 + 1] * y + Bf[j * 3 + 2] * s);
-        trig[r * FS + j] = f_to_bf(sinf(arg));
-        trig[r * FS + nf + j] = f_to_bf(cosf(arg));
+        float sv, cv;
+        sincosf(arg, &sv, &cv); // one argument reduction for both
+        trig[r * FS + j] = f_to_bf(sv);
+        trig[r * FS + nf + j] = f_to_bf(cv);
     }
     __syncthreads();
     const uint16_t xyz[3] = {f_to_bf(x), f_to_bf(y), f_to_bf(s)};
