@@ -130,6 +130,8 @@ def test_gradient_other_shapes(smrt, fourier, width, layers, outputs, n):
     (4, 64, 3, 2, 512),      # width 64
     (40, 64, 3, 3, 1024),    # 83 features padded to 128, width 64
     (40, 128, 4, 1, 2048),   # 128 features, width 128, four layers
+    (8, 128, 2, 1, 320),     # one hidden layer
+    (8, 64, 2, 2, 192),      # one hidden layer of width 64; 12 row blocks, fewer than a workgroup's waves
 ])
 def test_fused_forward_bitwise_equals_per_layer(smrt, fourier, width, layers, outputs, n):
     """The one-launch forward pass against one launch per layer: outputs and
