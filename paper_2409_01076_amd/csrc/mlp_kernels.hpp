@@ -406,6 +406,10 @@ struct FusedArgs {
     uint16_t* act[kFusedMaxLayers];          // A_l, [rows][H] bf16, hidden layers
     int blocks;                              // rows / 16
     FwdOut o;                                // output layer (N = 64)
+    // with the MSE target: W_{L-1} ([H][64] bf16, not transposed) and, when
+    // set, dZ_{L-2} = (dY W_{L-1}^T) silu'(Z_{L-2}) into dz_last ([rows][H])
+    const uint16_t* w_last;
+    uint16_t* dz_last;
 };
 
 // LDS elements of the packed transposed weights of such a network
@@ -459,11 +463,14 @@ __global__ void __launch_bounds__(FUSED_THREADS, 1) forward_fused(FusedArgs a)
 {
     static_assert(K0 % 64 == 0 && K0 <= KC && (H == 64 || H == 128), "fused forward shapes");
     constexpr int FJ = H / 16, WAVES = FUSED_THREADS / 64;
+    constexpr bool MSE = MODE == FWD_OUT_MSE;
     __shared__ __attribute__((aligned(16))) uint16_t Ws[kFusedWeightElems];
     __shared__ __attribute__((aligned(16))) float bs[kFusedBiasFloats];
+    __shared__ __attribute__((aligned(16))) uint16_t Wl[MSE ? H * 72 : 8]; // W_{L-1}, row stride 72
     __shared__ double lds[WAVES];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
     const int L = a.layers;
+    const bool dz = MSE && a.dz_last != nullptr;
     // stage every layer's W^T and bias
     {
         int off = 0;
@@ -476,6 +483,14 @@ __global__ void __launch_bounds__(FUSED_THREADS, 1) forward_fused(FusedArgs a)
             }
             for (int c = threadIdx.x; c < N; c += FUSED_THREADS) bs[l * 128 + c] = a.bias[l][c];
             off += N * (K + 8);
+        }
+        if constexpr (MSE) {
+            if (dz)
+                for (int c = threadIdx.x; c < H * 8; c += FUSED_THREADS) {
+                    const int row = c >> 3, k8 = (c & 7) * 8;
+                    *reinterpret_cast<u32x4*>(Wl + row * 72 + k8) =
+                        *reinterpret_cast<const u32x4*>(a.w_last + (int64_t)row * 64 + k8);
+                }
         }
     }
     __syncthreads();
@@ -490,6 +505,7 @@ __global__ void __launch_bounds__(FUSED_THREADS, 1) forward_fused(FusedArgs a)
         if (b + stride < a.blocks) load_rows(xn, a.X0, K0, (b + stride) * 16, 0, K0);
         const int64_t m = (int64_t)b * 16 + r;
         const uint16_t* W = Ws;
+        f32x4 zl[MSE ? FJ : 1]; // the last hidden layer's pre-activations
         for (int l = 0; l < L - 1; ++l) {
             f32x4 acc[FJ];
 #pragma unroll
@@ -512,6 +528,7 @@ __global__ void __launch_bounds__(FUSED_THREADS, 1) forward_fused(FusedArgs a)
                 for (int i = 0; i < 4; ++i) {
                     const float v = acc[j][i] + b4[i];
                     h[i] = v * sigmoid(v);
+                    if constexpr (MSE) zl[j][i] = v; // kept from the last hidden layer
                 }
                 pk[j] = make_uint2(pack_bf16(h[0], h[1]), pack_bf16(h[2], h[3]));
                 *reinterpret_cast<uint2*>(act + m * H + n) = pk[j];
@@ -522,6 +539,7 @@ __global__ void __launch_bounds__(FUSED_THREADS, 1) forward_fused(FusedArgs a)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
         rows_times_resident<4, H, H + 8>(acc, xf, W);
+        uint2 pdy[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int n = 16 * j + 4 * q;
@@ -533,14 +551,40 @@ __global__ void __launch_bounds__(FUSED_THREADS, 1) forward_fused(FusedArgs a)
                 h[i] = 0.f;
                 if (n + i < a.o.keep) {
                     a.o.y[m * a.o.keep + n + i] = v;
-                    if constexpr (MODE == FWD_OUT_MSE) {
+                    if constexpr (MSE) {
                         const float e = v - a.o.target[m * a.o.keep + n + i];
                         lsum += (double)e * e;
                         h[i] = a.o.scale * e;
                     }
                 }
             }
-            if constexpr (MODE == FWD_OUT_MSE) store_bf16x4(a.o.dy + m * 64 + n, h);
+            if constexpr (MSE) {
+                pdy[j] = make_uint2(pack_bf16(h[0], h[1]), pack_bf16(h[2], h[3]));
+                *reinterpret_cast<uint2*>(a.o.dy + m * 64 + n) = pdy[j];
+            }
+        }
+        if constexpr (MSE) {
+            if (dz) {
+                // the output layer's input gradient, with the backward pass's
+                // operands in its order: g = dY W_{L-1}^T from the bf16 dY,
+                // then dZ = g s (1 + z (1 - s)), s = sigmoid(z)
+                bf16x8 xg[KC / 32];
+                regroup_rows<4>(pdy, xg);
+                f32x4 g[FJ];
+#pragma unroll
+                for (int j = 0; j < FJ; ++j) g[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+                rows_times_resident<FJ, 64, 72>(g, xg, Wl);
+#pragma unroll
+                for (int j = 0; j < FJ; ++j) {
+                    float h[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const float zz = zl[j][i], s = sigmoid(zz);
+                        h[i] = g[j][i] * s * (1.0f + zz * (1.0f - s));
+                    }
+                    store_bf16x4(a.dz_last + m * H + 16 * j + 4 * q, h);
+                }
+            }
         }
 #pragma unroll
         for (int kk = 0; kk < KC / 32; ++kk) xf[kk] = xn[kk];

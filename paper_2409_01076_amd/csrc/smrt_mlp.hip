@@ -145,6 +145,7 @@ struct smrt_mlp {
     int64_t adam_steps = 0;
     int loss_parts = 0; // squared-error partials written by the last forward pass with a target
     bool fused = true;  // one launch for the whole forward pass where the network fits
+    bool dz_ready = false; // the last forward pass also wrote dZ_{L-2} into dz(0)
     bool has_params = false;
     std::vector<double> loss_host;
 
@@ -232,6 +233,9 @@ int forward_fused_launch(smrt_mlp* m, int n, float* out, const float* target)
         a.o.scale = 2.0f / ((float)n * L.outputs);
         a.o.loss = m->loss_part();
         m->loss_parts = groups;
+        // the output layer's input gradient in the same launch
+        a.w_last = m->wbf() + L.w_off[L.layers - 1];
+        a.dz_last = m->dz(0);
     }
     const int mse = target != nullptr;
     hipStream_t s = m->stream;
@@ -239,6 +243,7 @@ int forward_fused_launch(smrt_mlp* m, int n, float* out, const float* target)
     if (L.k0 == K0 && L.width == H) {                                                        \
         if (mse) forward_fused<K0, H, FWD_OUT_MSE><<<groups, FUSED_THREADS, 0, s>>>(a);        \
         else forward_fused<K0, H, FWD_OUT><<<groups, FUSED_THREADS, 0, s>>>(a);                \
+        m->dz_ready = mse;                                                                   \
         return after_launch("forward_fused");                                                \
     }
     SMRT_FUSED(64, 128)
@@ -257,6 +262,7 @@ int forward(smrt_mlp* m, const float* pts, int n, float* out, const float* targe
     using namespace smrt::mlp;
     const MlpLayout& L = m->L;
     hipStream_t s = m->stream;
+    m->dz_ready = false;
     features<<<n / 64, 256, 0, s>>>(pts, m->fourier(), L.nf, n, L.k0, m->x0());
     int rc = after_launch("features");
     if (rc) return rc;
@@ -369,6 +375,14 @@ int backward(smrt_mlp* m, int n, const smrt::mlp::AdamArgs* adam, double* loss)
             rc = launch_weight_grad(s, ga, splits);
             if (rc) return rc;
             break;
+        }
+        if (l == L.layers - 1 && m->dz_ready) {
+            // the fused forward pass already wrote dZ_{l-1} into dz(0)
+            rc = launch_weight_grad(s, ga, splits);
+            if (rc) return rc;
+            dcur = m->dz(0);
+            flip = 1;
+            continue;
         }
         // dZ_{l-1} = (dZ_l W_l^T) silu'(Z_{l-1}), Z_{l-1} = A_{l-2} W_{l-1} + b_{l-1},
         // beside the row-block partials of layer l's W and b gradient
